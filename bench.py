@@ -1,0 +1,169 @@
+"""Benchmark of the D2Q9 MRT lattice Boltzmann step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload waves4096]
+
+Workload (default): 4096 x 4096 periodic lattice, FP32 deviation storage and
+arithmetic, Table 5 group A relaxation rates, a plane acoustic wave
+(k = 2 pi 8 / 4096 along x, amplitude 1e-4) plus a shear wave (u_y amplitude
+1e-4) on a mean flow u_x = 0.1 c_s; the job is 2000 steps.  One "step" is one
+fused collide-and-stream pass over the whole lattice.  The inputs are resident
+in HBM before timing starts; the timed region is K consecutive steps on the
+lattice's stream, bracketed by device synchronisation and HIP events.
+
+Prints one JSON line: MLUPS, the roofline of the step kernel (algorithmic
+bytes 2 * 9 * sizeof(storage) per lattice update over its measured average
+duration, against the 8 TB/s HBM peak), measured HBM traffic from the
+committed rocprofv3 counter summary when it matches the current kernel
+source, and the FP64 CPU oracle timed on a bounded sample of the same
+workload on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "MLUPS & % HBM roofline (D2Q9 MRT, 1 GPU); served p50/p99 vs plain at equal error"
+STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1107_4543_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode())
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def read_traffic(workload, storage):
+    """Measured HBM bytes per launch from the committed counter summary, or
+    None when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_step_{storage}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def build_waves4096(storage):
+    import numpy as np
+    import torch
+
+    import lbm_inputs
+    from paper_1107_4543_amd import Lattice
+    w = lbm_inputs.WORKLOADS["waves4096"]
+    s = lbm_inputs.PRESETS[w["relax"]]
+    rates = [s["s_e"], s["s_eps"], s["s_q"], s["s_nu"]]
+    nx, ny = w["nx"], w["ny"]
+    rho, ux, uy = lbm_inputs.plane_waves(nx, 1, w["mode"], w["amplitude"], w["shear_amplitude"], w["u0x"])
+    fields = [torch.from_numpy(np.broadcast_to(a, (ny, nx)).copy()).cuda() for a in (rho, ux, uy)]
+    lat = Lattice(nx, ny, *rates, storage=storage, u0=(w["u0x"], 0.0), device="cuda:0")
+    lat.init(*fields)
+    del fields
+    cfg = {"workload": "waves4096", "nx": nx, "ny": ny, "storage": storage,
+           "relaxation": "Table 5 group A", "u0x": w["u0x"], "mode": w["mode"],
+           "amplitude": w["amplitude"], "job_steps": w["steps"]}
+    return lat, cfg, rates, (rho, ux, uy), w
+
+
+def cpu_baseline(rates, fields1, nx, ny, u0x, budget_s):
+    """FP64 oracle (as it stands) on the full lattice for as many whole steps
+    as fit in about budget_s seconds (at least one)."""
+    import numpy as np
+
+    import oracle
+    rho, ux, uy = (np.ascontiguousarray(np.broadcast_to(a, (ny, nx))) for a in fields1)
+    f = oracle.init(rho, ux, uy)
+    del rho, ux, uy
+    steps, elapsed = 0, 0.0
+    while elapsed < budget_s:
+        t0 = time.perf_counter()
+        f = oracle.run(f, rates, 1)
+        elapsed += time.perf_counter() - t0
+        steps += 1
+    return {"value": nx * ny * steps / elapsed / 1e6, "unit": "MLUPS", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle (unfused collide then stream) on the full {nx}x{ny} lattice, "
+                      f"{steps} step(s), {elapsed:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16", "bf16"])
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work (0 = skip)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the lattice path is single-GPU in this build "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.init()
+
+    lat, cfg, rates, fields1, w = build_waves4096(args.storage)
+    tuned = None
+    if not args.no_tune:
+        tuned, _ = lat.tune(reps=5)
+    cfg["launch"] = lat.launch
+
+    stream = lat.stream
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lat.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    st, diag = lat.diagnostics()
+    assert st == 0, "non-finite state after the timed steps"
+
+    cells = lat.nx * lat.ny
+    mlups = cells * args.steps / (ms / 1e3) / 1e6
+    us_per_launch = 1e3 * ms / args.steps
+    alg_bytes = 2 * 9 * STORE_BYTES[args.storage] * cells
+    achieved = alg_bytes / (us_per_launch * 1e-6) / 1e9
+    traffic = read_traffic("waves4096", args.storage)
+
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.storage, "data": "synthetic", "config": cfg,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                     "kernel": "k_step (fused collide + pull stream)",
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "avg_launch_us": round(us_per_launch, 3)},
+    }
+    if args.cpu_budget > 0:
+        out["cpu_baseline"] = cpu_baseline(rates, fields1, lat.nx, lat.ny, w["u0x"], args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

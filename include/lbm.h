@@ -1,0 +1,215 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) D2Q9 multi-relaxation-time lattice
+ * Boltzmann library.
+ *
+ * The scheme is the standard D2Q9 MRT model of Xu & Sagaut, "Optimal
+ * low-dispersion low-dissipation LBM schemes for computational
+ * aeroacoustics":
+ *   evolution      f_i(x + v_i, t + 1) = f_i + Lambda_ij (f^eq_j - f_j)     (Sec. 2.1, Eq. blbs)
+ *   relaxation     Lambda = M^{-1} S M, S = diag(0,0,0,s_e,s_eps,s_q,s_q,s_nu,s_nu)
+ *                                                                         (Sec. 2.1; Sec. 2.3)
+ *   equilibrium    m^eq = (rho, jx, jy, -2rho + 3|j|^2/rho, rho - 3|j|^2/rho,
+ *                          -jx, -jy, (jx^2 - jy^2)/rho, jx jy/rho)         (Sec. 2.3)
+ *   lattice        periodic nx x ny, unit spacing and time step             (Sec. 2.1; Sec. 5)
+ *
+ * Velocity order (fixes every population layout below):
+ *   v_0=(0,0) v_1=(1,0) v_2=(0,1) v_3=(-1,0) v_4=(0,-1)
+ *   v_5=(1,1) v_6=(-1,1) v_7=(-1,-1) v_8=(1,-1).
+ *
+ * Conventions that hold for every function:
+ *   - Every function returns lbm_status (0 == LBM_OK) unless stated; nothing
+ *     throws across the ABI.  On failure lbm_last_error() describes it.
+ *   - "device pointer" = memory on the GPU the lattice lives on, "host
+ *     pointer" = ordinary CPU memory.  Field arrays are contiguous, row-major
+ *     [ny][nx] (x fastest) in IEEE double; population arrays are [9][ny][nx].
+ *   - The caller owns every buffer, including the device workspace and the
+ *     stream; the library owns only its host-side handle objects.
+ *   - Functions marked "enqueued" only enqueue GPU work on the lattice's
+ *     stream and return; functions marked "syncs" wait for that stream.
+ *   - A handle is used from one host thread at a time.
+ *   - The logical state at integer t is the pre-collision f(t).
+ */
+#ifndef LBM_H_
+#define LBM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define LBM_API __attribute__((visibility("default")))
+#else
+#define LBM_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lbm_status;
+#define LBM_OK            0
+#define LBM_E_INVAL      (-1)  /* invalid argument or descriptor                 */
+#define LBM_E_NOMEM      (-2)  /* workspace too small / capacity exceeded         */
+#define LBM_E_HIP        (-3)  /* a HIP runtime call failed                       */
+#define LBM_E_NONFINITE  (-4)  /* diagnostics found non-finite populations        */
+#define LBM_E_STATE      (-5)  /* call out of order (e.g. step before init)       */
+
+/* Storage type of the population deviations held in HBM. */
+#define LBM_STORE_F64   0
+#define LBM_STORE_F32   1
+#define LBM_STORE_F16   2
+#define LBM_STORE_BF16  3
+/* Arithmetic type of the collision. */
+#define LBM_COMPUTE_F64 0
+#define LBM_COMPUTE_F32 1
+
+/* scale_exp value asking lbm_init_equilibrium to choose the storage scale. */
+#define LBM_SCALE_AUTO  INT32_MIN
+
+/*
+ * Lattice descriptor.
+ *   nx, ny      lattice size, >= 1 each, nx * ny < 2^31.
+ *   storage     LBM_STORE_*.  The library stores the deviation
+ *               g_i = (f_i - f^eq_i(rho0, u0)) * 2^scale_exp, i.e. the
+ *               fluctuating part about the uniform state (Sec. 4.1, Eq.
+ *               perturb-f), rounded to nearest even.
+ *   compute     LBM_COMPUTE_*.  Allowed pairs: (F64,F64), (F64,F32),
+ *               (F32,F32), (F16,F32), (BF16,F32).  With F64 storage and F32
+ *               compute the increment of the collision is evaluated in F32
+ *               and added to the stored value in F64.
+ *   s_e, s_eps, s_q, s_nu
+ *               relaxation rates, each in (0, 2]  (Sec. 2.1 stability range,
+ *               widened to include 2 as in Sec. 3.2 and Table 4).
+ *   rho0 > 0, u0x, u0y
+ *               uniform base state of the deviation storage; any finite value
+ *               is correct, values near the flow's mean minimise rounding.
+ *   scale_exp   p in [-60, 60], or LBM_SCALE_AUTO (F16/BF16: chosen at init
+ *               so that max|g| * 2^p is about 2^13; F64/F32: 0).
+ *   flags       reserved, must be 0.
+ */
+typedef struct lbm_desc {
+    int32_t nx, ny;
+    int32_t storage;
+    int32_t compute;
+    double s_e, s_eps, s_q, s_nu;
+    double rho0, u0x, u0y;
+    int32_t scale_exp;
+    int32_t flags;
+} lbm_desc;
+
+typedef struct lbm_lattice lbm_lattice;
+
+/* Launch shape of the fused step kernel (chosen by lbm_tune or set by hand).
+ *   variant   0 = one cell per lane, 1 = two cells per lane (x pairs),
+ *             2 = four cells per lane (x quads)
+ *   block_x   lanes along x per workgroup (multiple of 64 over the lanes)
+ *   block_y   rows per workgroup pass
+ *   rows      rows each lane processes (tile height = block_y * rows)
+ *   xcd_remap 1 = remap workgroup ids so that neighbouring tiles run on the
+ *             same XCD (shared L2), 0 = hardware order. */
+typedef struct lbm_launch {
+    int32_t variant;
+    int32_t block_x;
+    int32_t block_y;
+    int32_t rows;
+    int32_t xcd_remap;
+    int32_t reserved;
+} lbm_launch;
+
+/* ---- status and helpers ------------------------------------------------ */
+
+/* Static text for a status code; never NULL. */
+LBM_API const char *lbm_status_string(lbm_status s);
+/* Message of the most recent failure on the calling thread ("" if none). */
+LBM_API const char *lbm_last_error(void);
+/* s_nu = 1 / (3 nu + 1/2): sigma = 1/s - 1/2 (Sec. 2.3) and nu = sigma_nu / 3
+ * (first-order dissipation matrix, Sec. 2.3.1; Table 4 prints both).
+ * Returns NaN for nu outside [0, inf). */
+LBM_API double lbm_s_from_nu(double nu);
+
+/* ---- single lattice ---------------------------------------------------- */
+
+/* Device workspace bytes a lattice with this descriptor needs: two
+ * population buffers [9][ny][pitch] of the storage type (pitch = nx rounded
+ * up to 64 elements), reduction scratch and padding.  0 if invalid. */
+LBM_API size_t lbm_workspace_bytes(const lbm_desc *desc);
+
+/* Creates a lattice handle on the current HIP device.
+ *   dev_ws    device pointer, 256-byte aligned, >= lbm_workspace_bytes(desc)
+ *             bytes, owned by the caller and not freed by lbm_destroy.
+ *   stream    hipStream_t to enqueue on (NULL = the null stream).
+ *   out       receives the handle.
+ * Errors: LBM_E_INVAL (descriptor, alignment), LBM_E_NOMEM (ws_bytes). */
+LBM_API lbm_status lbm_create(const lbm_desc *desc, void *dev_ws, size_t ws_bytes, void *stream,
+                      lbm_lattice **out);
+/* Releases the handle (not the workspace).  Does not wait for the stream. */
+LBM_API lbm_status lbm_destroy(lbm_lattice *lat);
+/* Replaces the stream used by later calls. */
+LBM_API lbm_status lbm_set_stream(lbm_lattice *lat, void *stream);
+/* Copies the descriptor, with scale_exp resolved once init has run. */
+LBM_API lbm_status lbm_get_desc(const lbm_lattice *lat, lbm_desc *out);
+
+/* Equilibrium initialisation from macroscopic fields (Sec. 5.2 initial
+ * condition): f(x, 0) = M^{-1} m^eq(rho, rho u).  rho, ux, uy: device
+ * pointers [ny][nx] FP64; rho must be > 0 and all values finite (not checked
+ * on the device; non-finite input shows up in lbm_diagnostics).  Sets t = 0.
+ * Enqueued; syncs once when scale_exp is LBM_SCALE_AUTO. */
+LBM_API lbm_status lbm_init_equilibrium(lbm_lattice *lat, const double *rho, const double *ux,
+                                const double *uy);
+
+/* Advances n >= 0 steps of the fused collide-and-pull-stream update
+ * (Sec. 2.1, Eq. blbs with Lambda = M^{-1} S M; pull form of Sec. 2.2, Eq.
+ * l-mrt-lbs).  Enqueued.  LBM_E_STATE before init. */
+LBM_API lbm_status lbm_step(lbm_lattice *lat, int64_t n);
+
+/* Macroscopic fields of the current state (Sec. 2.1, Eq. q-macro):
+ * rho = sum_i f_i, u = (sum_i v_i f_i) / rho, evaluated in FP64.
+ * rho, ux, uy: device pointers [ny][nx] FP64.  Enqueued. */
+LBM_API lbm_status lbm_read_moments(lbm_lattice *lat, double *rho, double *ux, double *uy);
+
+/* Global FP64 diagnostics of the current state (host pointer out[4]):
+ *   out[0] = sum_x (rho - rho0), out[1] = sum_x (jx - rho0 u0x),
+ *   out[2] = sum_x (jy - rho0 u0y)   (the collision invariants of Sec. 2.1,
+ *   Eq. eq_conservative; constant in exact arithmetic),
+ *   out[3] = number of non-finite stored values.
+ * Syncs.  Returns LBM_E_NONFINITE when out[3] > 0 (out is still filled). */
+LBM_API lbm_status lbm_diagnostics(lbm_lattice *lat, double out[4]);
+
+/* FP64 Fourier projection of the population deviations onto the lattice mode
+ * k = 2 pi (mx / nx, my / ny), the plane-wave amplitudes of the von Neumann
+ * analysis (Sec. 4.1, Eq. perturb-w-f):
+ *   dev_out[2i] + I dev_out[2i+1] = sum_x (f_i(x,t) - f^eq_i(rho0,u0)) e^{-I k.x},
+ * i = 0..8 (18 doubles, device pointer).  Enqueued. */
+LBM_API lbm_status lbm_project(lbm_lattice *lat, int32_t mx, int32_t my, double *dev_out);
+
+/* Pre-collision populations f(t) as FP64, device pointer [9][ny][nx].  Enqueued. */
+LBM_API lbm_status lbm_read_populations(lbm_lattice *lat, double *dev_f);
+/* Replaces the state by FP64 populations (rounded to the storage type);
+ * t is left unchanged.  Enqueued. */
+LBM_API lbm_status lbm_write_populations(lbm_lattice *lat, const double *dev_f);
+
+/* Bytes of the raw state (the current buffer in its storage type). */
+LBM_API size_t lbm_state_bytes(const lbm_lattice *lat);
+/* Bitwise checkpoint of the raw state into / from a device buffer of
+ * lbm_state_bytes bytes; load also sets t.  Enqueued. */
+LBM_API lbm_status lbm_save_state(lbm_lattice *lat, void *dev_dst);
+LBM_API lbm_status lbm_load_state(lbm_lattice *lat, const void *dev_src, int64_t t);
+
+/* Steps taken since init (or the t given to lbm_load_state). */
+LBM_API int64_t lbm_time(const lbm_lattice *lat);
+
+/* Launch shape of the step kernel for this lattice. */
+LBM_API lbm_status lbm_get_launch(const lbm_lattice *lat, lbm_launch *out);
+/* LBM_E_INVAL if the shape is not supported for this lattice. */
+LBM_API lbm_status lbm_set_launch(lbm_lattice *lat, const lbm_launch *cfg);
+/* Times every supported launch shape on this lattice (reps launches each,
+ * the state is left unchanged) and selects the fastest.  best/best_us may
+ * be NULL.  Syncs. */
+LBM_API lbm_status lbm_tune(lbm_lattice *lat, int32_t reps, lbm_launch *best, double *best_us);
+/* Times n launches of the current shape (state unchanged; syncs). */
+LBM_API lbm_status lbm_time_launches(lbm_lattice *lat, int32_t n, double *avg_us);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H_ */

@@ -1,0 +1,437 @@
+// C ABI and host runtime of the D2Q9 MRT lattice Boltzmann library.
+//
+// The library owns only host-side handles.  Every device byte it touches is
+// carved from the caller's workspace:
+//   [ buffer 0 : 9 planes ][ buffer 1 : 9 planes ][ reduction scratch ]
+// each part 256-byte aligned.  Kernels are enqueued on the caller's stream.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "lbm_device.hpp"
+#include "lbm_internal.hpp"
+
+using lbm::View;
+
+struct lbm_lattice {
+    View v;
+    lbm_desc desc;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    size_t buf_bytes = 0;      // bytes of one buffer (aligned)
+    size_t state_bytes = 0;    // bytes of one buffer's planes (exact)
+    void *buf[2] = {nullptr, nullptr};
+    int cur = 0;
+    double *partials = nullptr;
+    double *result = nullptr;
+    hipStream_t stream = nullptr;
+    int64_t t = 0;
+    bool initialized = false;
+    lbm_launch launch{};
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+lbm_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(LBM_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+bool rate_ok(double s) { return isfinite(s) && s > 0.0 && s <= 2.0; }
+
+lbm_status validate(const lbm_desc *d)
+{
+    if (!d) return fail(LBM_E_INVAL, "desc is NULL");
+    if (d->nx < 1 || d->ny < 1) return fail(LBM_E_INVAL, "nx, ny must be >= 1 (got %d, %d)", d->nx, d->ny);
+    const int64_t pitch = ((int64_t)d->nx + 63) / 64 * 64;
+    if (pitch * (int64_t)d->ny >= ((int64_t)1 << 31))
+        return fail(LBM_E_INVAL, "lattice too large: pitch * ny must be < 2^31");
+    if (lbm::storage_bytes(d->storage) == 0) return fail(LBM_E_INVAL, "unknown storage %d", d->storage);
+    if (d->compute != LBM_COMPUTE_F64 && d->compute != LBM_COMPUTE_F32)
+        return fail(LBM_E_INVAL, "unknown compute %d", d->compute);
+    if (d->compute == LBM_COMPUTE_F64 && d->storage != LBM_STORE_F64)
+        return fail(LBM_E_INVAL, "FP64 compute requires FP64 storage");
+    if (!rate_ok(d->s_e) || !rate_ok(d->s_eps) || !rate_ok(d->s_q) || !rate_ok(d->s_nu))
+        return fail(LBM_E_INVAL, "relaxation rates must lie in (0, 2] (s_e=%g s_eps=%g s_q=%g s_nu=%g)", d->s_e,
+                    d->s_eps, d->s_q, d->s_nu);
+    if (!isfinite(d->rho0) || d->rho0 <= 0.0) return fail(LBM_E_INVAL, "rho0 must be finite and > 0");
+    if (!isfinite(d->u0x) || !isfinite(d->u0y)) return fail(LBM_E_INVAL, "u0 must be finite");
+    if (d->scale_exp != LBM_SCALE_AUTO && (d->scale_exp < -60 || d->scale_exp > 60))
+        return fail(LBM_E_INVAL, "scale_exp must be in [-60, 60] or LBM_SCALE_AUTO");
+    if (d->flags != 0) return fail(LBM_E_INVAL, "flags must be 0");
+    return LBM_OK;
+}
+
+void layout(const lbm_desc *d, int32_t *pitch, int64_t *plane, size_t *state_bytes, size_t *buf_bytes)
+{
+    *pitch = (d->nx + 63) / 64 * 64;
+    *plane = (int64_t)*pitch * d->ny;
+    *state_bytes = (size_t)9 * (size_t)*plane * lbm::storage_bytes(d->storage);
+    *buf_bytes = align256(*state_bytes);
+}
+
+void set_scale(View &v, int p)
+{
+    v.scale_exp = p;
+    v.scale = ldexp(1.0, p);
+    v.inv_scale = ldexp(1.0, -p);
+}
+
+lbm_launch default_launch(const View &)
+{
+    lbm_launch c{};
+    c.variant = 0;
+    c.block_x = 64;
+    c.block_y = 4;
+    c.rows = 1;
+    c.xcd_remap = 1;
+    return c;
+}
+
+// Candidate shapes for the tuner.
+std::vector<lbm_launch> candidates(const View &v)
+{
+    std::vector<lbm_launch> out;
+    const int variants[] = {0, 1, 2, 3};
+    const int bxs[] = {64, 128, 256};
+    const int bys[] = {1, 2, 4};
+    const int rows[] = {1, 2, 4};
+    for (int var : variants)
+        for (int bx : bxs)
+            for (int by : bys)
+                for (int r : rows)
+                    for (int remap = 0; remap < 2; ++remap) {
+                        if (bx * by > 512) continue;
+                        lbm_launch c{};
+                        c.variant = var;
+                        c.block_x = bx;
+                        c.block_y = by;
+                        c.rows = r;
+                        c.xcd_remap = remap;
+                        if (lbm::step_shape_supported(v, c)) out.push_back(c);
+                    }
+    return out;
+}
+
+lbm_status time_shape(lbm_lattice *L, const lbm_launch &c, int reps, double *us)
+{
+    hipEvent_t e0, e1;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    lbm_status st = LBM_OK;
+    // Every launch reads the current buffer and writes the other one, so
+    // the state is unchanged and the other buffer ends as the next step.
+    for (int k = 0; k < 2 && st == LBM_OK; ++k)
+        if ((e = lbm::launch_step(L->v, L->buf[L->cur], L->buf[L->cur ^ 1], c, L->stream)) != hipSuccess)
+            st = hip_fail(e, "step launch");
+    if (st == LBM_OK && (e = hipEventRecord(e0, L->stream)) != hipSuccess) st = hip_fail(e, "hipEventRecord");
+    for (int k = 0; k < reps && st == LBM_OK; ++k)
+        if ((e = lbm::launch_step(L->v, L->buf[L->cur], L->buf[L->cur ^ 1], c, L->stream)) != hipSuccess)
+            st = hip_fail(e, "step launch");
+    if (st == LBM_OK && (e = hipEventRecord(e1, L->stream)) != hipSuccess) st = hip_fail(e, "hipEventRecord");
+    if (st == LBM_OK && (e = hipEventSynchronize(e1)) != hipSuccess) st = hip_fail(e, "hipEventSynchronize");
+    float ms = 0.f;
+    if (st == LBM_OK && (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) st = hip_fail(e, "hipEventElapsedTime");
+    if (st == LBM_OK) *us = 1000.0 * ms / reps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lbm_status_string(lbm_status s)
+{
+    switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_E_INVAL: return "invalid argument";
+    case LBM_E_NOMEM: return "workspace too small";
+    case LBM_E_HIP: return "HIP runtime error";
+    case LBM_E_NONFINITE: return "non-finite populations";
+    case LBM_E_STATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+
+double lbm_s_from_nu(double nu)
+{
+    if (!(nu >= 0.0) || !isfinite(nu)) return NAN;
+    return 1.0 / (3.0 * nu + 0.5);
+}
+
+size_t lbm_workspace_bytes(const lbm_desc *desc)
+{
+    if (validate(desc) != LBM_OK) return 0;
+    int32_t pitch;
+    int64_t plane;
+    size_t sb, bb;
+    layout(desc, &pitch, &plane, &sb, &bb);
+    return 2 * bb + align256(lbm::kScratchBytes);
+}
+
+lbm_status lbm_create(const lbm_desc *desc, void *dev_ws, size_t ws_bytes, void *stream, lbm_lattice **out)
+{
+    if (!out) return fail(LBM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    lbm_status st = validate(desc);
+    if (st != LBM_OK) return st;
+    if (!dev_ws || ((uintptr_t)dev_ws & 255u)) return fail(LBM_E_INVAL, "workspace must be non-NULL and 256-byte aligned");
+    const size_t need = lbm_workspace_bytes(desc);
+    if (ws_bytes < need) return fail(LBM_E_NOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+
+    lbm_lattice *L = new (std::nothrow) lbm_lattice();
+    if (!L) return fail(LBM_E_NOMEM, "host allocation failed");
+    L->desc = *desc;
+    View &v = L->v;
+    v.nx = desc->nx;
+    v.ny = desc->ny;
+    v.storage = desc->storage;
+    v.compute = desc->compute;
+    size_t sb, bb;
+    layout(desc, &v.pitch, &v.plane, &sb, &bb);
+    v.s_e = desc->s_e;
+    v.s_eps = desc->s_eps;
+    v.s_q = desc->s_q;
+    v.s_nu = desc->s_nu;
+    v.rho0 = desc->rho0;
+    v.j0x = desc->rho0 * desc->u0x;
+    v.j0y = desc->rho0 * desc->u0y;
+    // f^eq(rho0, j0) = M^{-1} m^eq(rho0, j0): the deviation formula about a zero base.
+    lbm::Relax<double> zero{};
+    double m[9];
+    lbm::delta_meq<double>(v.rho0, v.j0x, v.j0y, zero, m);
+    lbm::back_transform<double>(m, v.fbase);
+    set_scale(v, desc->scale_exp == LBM_SCALE_AUTO ? 0 : desc->scale_exp);
+    L->ws = (char *)dev_ws;
+    L->ws_bytes = ws_bytes;
+    L->buf_bytes = bb;
+    L->state_bytes = sb;
+    L->buf[0] = L->ws;
+    L->buf[1] = L->ws + bb;
+    L->partials = (double *)(L->ws + 2 * bb);
+    L->result = L->partials + (size_t)lbm::kRedBlocks * lbm::kRedWidth;
+    L->stream = (hipStream_t)stream;
+    L->launch = default_launch(v);
+    *out = L;
+    return LBM_OK;
+}
+
+lbm_status lbm_destroy(lbm_lattice *lat)
+{
+    if (!lat) return fail(LBM_E_INVAL, "lattice is NULL");
+    delete lat;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_stream(lbm_lattice *lat, void *stream)
+{
+    if (!lat) return fail(LBM_E_INVAL, "lattice is NULL");
+    lat->stream = (hipStream_t)stream;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_desc(const lbm_lattice *lat, lbm_desc *out)
+{
+    if (!lat || !out) return fail(LBM_E_INVAL, "NULL argument");
+    *out = lat->desc;
+    if (lat->initialized || lat->desc.scale_exp != LBM_SCALE_AUTO) out->scale_exp = lat->v.scale_exp;
+    return LBM_OK;
+}
+
+lbm_status lbm_init_equilibrium(lbm_lattice *lat, const double *rho, const double *ux, const double *uy)
+{
+    if (!lat || !rho || !ux || !uy) return fail(LBM_E_INVAL, "NULL argument");
+    hipError_t e;
+    const bool sixteen = lat->v.storage == LBM_STORE_F16 || lat->v.storage == LBM_STORE_BF16;
+    if (lat->desc.scale_exp == LBM_SCALE_AUTO) {
+        int p = 0;
+        if (sixteen) {
+            if ((e = lbm::launch_init(lat->v, rho, ux, uy, nullptr, lat->partials, lat->result, true, lat->stream)) !=
+                hipSuccess)
+                return hip_fail(e, "init (measure)");
+            double mx = 0.0;
+            if ((e = hipMemcpyAsync(&mx, lat->result, sizeof(double), hipMemcpyDeviceToHost, lat->stream)) !=
+                hipSuccess)
+                return hip_fail(e, "hipMemcpyAsync");
+            if ((e = hipStreamSynchronize(lat->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            if (!isfinite(mx)) return fail(LBM_E_INVAL, "initial fields are not finite");
+            if (mx > 0.0) p = (int)floor(log2(8192.0 / mx));
+            p = std::max(-60, std::min(60, p));
+        }
+        set_scale(lat->v, p);
+    }
+    if ((e = lbm::launch_init(lat->v, rho, ux, uy, lat->buf[0], lat->partials, lat->result, false, lat->stream)) !=
+        hipSuccess)
+        return hip_fail(e, "init");
+    lat->cur = 0;
+    lat->t = 0;
+    lat->initialized = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_lattice *lat, int64_t n)
+{
+    if (!lat) return fail(LBM_E_INVAL, "lattice is NULL");
+    if (n < 0) return fail(LBM_E_INVAL, "n must be >= 0");
+    if (!lat->initialized) return fail(LBM_E_STATE, "lbm_step before lbm_init_equilibrium");
+    for (int64_t k = 0; k < n; ++k) {
+        hipError_t e = lbm::launch_step(lat->v, lat->buf[lat->cur], lat->buf[lat->cur ^ 1], lat->launch, lat->stream);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        lat->cur ^= 1;
+        lat->t += 1;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_read_moments(lbm_lattice *lat, double *rho, double *ux, double *uy)
+{
+    if (!lat || !rho || !ux || !uy) return fail(LBM_E_INVAL, "NULL argument");
+    if (!lat->initialized) return fail(LBM_E_STATE, "read before init");
+    hipError_t e = lbm::launch_moments(lat->v, lat->buf[lat->cur], rho, ux, uy, lat->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "moments");
+}
+
+lbm_status lbm_diagnostics(lbm_lattice *lat, double out[4])
+{
+    if (!lat || !out) return fail(LBM_E_INVAL, "NULL argument");
+    if (!lat->initialized) return fail(LBM_E_STATE, "diagnostics before init");
+    hipError_t e = lbm::launch_diagnostics(lat->v, lat->buf[lat->cur], lat->partials, lat->result, lat->stream);
+    if (e != hipSuccess) return hip_fail(e, "diagnostics");
+    double h[4];
+    if ((e = hipMemcpyAsync(h, lat->result, sizeof h, hipMemcpyDeviceToHost, lat->stream)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync");
+    if ((e = hipStreamSynchronize(lat->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    for (int k = 0; k < 3; ++k) out[k] = h[k] * lat->v.inv_scale;
+    out[3] = h[3];
+    if (h[3] > 0.0) return fail(LBM_E_NONFINITE, "%.0f non-finite stored values at t=%lld", h[3], (long long)lat->t);
+    return LBM_OK;
+}
+
+lbm_status lbm_project(lbm_lattice *lat, int32_t mx, int32_t my, double *dev_out)
+{
+    if (!lat || !dev_out) return fail(LBM_E_INVAL, "NULL argument");
+    if (!lat->initialized) return fail(LBM_E_STATE, "project before init");
+    hipError_t e = lbm::launch_project(lat->v, lat->buf[lat->cur], mx, my, lat->partials, dev_out, lat->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "project");
+}
+
+lbm_status lbm_read_populations(lbm_lattice *lat, double *dev_f)
+{
+    if (!lat || !dev_f) return fail(LBM_E_INVAL, "NULL argument");
+    if (!lat->initialized) return fail(LBM_E_STATE, "read before init");
+    hipError_t e = lbm::launch_read_populations(lat->v, lat->buf[lat->cur], dev_f, lat->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "read populations");
+}
+
+lbm_status lbm_write_populations(lbm_lattice *lat, const double *dev_f)
+{
+    if (!lat || !dev_f) return fail(LBM_E_INVAL, "NULL argument");
+    if (!lat->initialized && lat->desc.scale_exp == LBM_SCALE_AUTO &&
+        (lat->v.storage == LBM_STORE_F16 || lat->v.storage == LBM_STORE_BF16))
+        return fail(LBM_E_STATE, "16-bit storage with automatic scale: init before writing populations");
+    hipError_t e = lbm::launch_write_populations(lat->v, dev_f, lat->buf[lat->cur], lat->stream);
+    if (e != hipSuccess) return hip_fail(e, "write populations");
+    lat->initialized = true;
+    return LBM_OK;
+}
+
+size_t lbm_state_bytes(const lbm_lattice *lat) { return lat ? lat->state_bytes : 0; }
+
+lbm_status lbm_save_state(lbm_lattice *lat, void *dev_dst)
+{
+    if (!lat || !dev_dst) return fail(LBM_E_INVAL, "NULL argument");
+    if (!lat->initialized) return fail(LBM_E_STATE, "save before init");
+    hipError_t e = hipMemcpyAsync(dev_dst, lat->buf[lat->cur], lat->state_bytes, hipMemcpyDeviceToDevice, lat->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "hipMemcpyAsync");
+}
+
+lbm_status lbm_load_state(lbm_lattice *lat, const void *dev_src, int64_t t)
+{
+    if (!lat || !dev_src) return fail(LBM_E_INVAL, "NULL argument");
+    if (t < 0) return fail(LBM_E_INVAL, "t must be >= 0");
+    if (!lat->initialized && lat->desc.scale_exp == LBM_SCALE_AUTO &&
+        (lat->v.storage == LBM_STORE_F16 || lat->v.storage == LBM_STORE_BF16))
+        return fail(LBM_E_STATE, "16-bit storage with automatic scale: init before loading a state");
+    hipError_t e = hipMemcpyAsync(lat->buf[lat->cur], dev_src, lat->state_bytes, hipMemcpyDeviceToDevice, lat->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    lat->t = t;
+    lat->initialized = true;
+    return LBM_OK;
+}
+
+int64_t lbm_time(const lbm_lattice *lat) { return lat ? lat->t : -1; }
+
+lbm_status lbm_get_launch(const lbm_lattice *lat, lbm_launch *out)
+{
+    if (!lat || !out) return fail(LBM_E_INVAL, "NULL argument");
+    *out = lat->launch;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_launch(lbm_lattice *lat, const lbm_launch *cfg)
+{
+    if (!lat || !cfg) return fail(LBM_E_INVAL, "NULL argument");
+    if (!lbm::step_shape_supported(lat->v, *cfg))
+        return fail(LBM_E_INVAL, "launch shape (variant %d, %dx%d, rows %d) not supported for nx=%d", cfg->variant,
+                    cfg->block_x, cfg->block_y, cfg->rows, lat->v.nx);
+    lat->launch = *cfg;
+    return LBM_OK;
+}
+
+lbm_status lbm_time_launches(lbm_lattice *lat, int32_t n, double *avg_us)
+{
+    if (!lat || !avg_us || n < 1) return fail(LBM_E_INVAL, "bad argument");
+    if (!lat->initialized) return fail(LBM_E_STATE, "time before init");
+    return time_shape(lat, lat->launch, n, avg_us);
+}
+
+lbm_status lbm_tune(lbm_lattice *lat, int32_t reps, lbm_launch *best, double *best_us)
+{
+    if (!lat || reps < 1) return fail(LBM_E_INVAL, "bad argument");
+    if (!lat->initialized) return fail(LBM_E_STATE, "tune before init");
+    double best_t = INFINITY;
+    lbm_launch best_c = lat->launch;
+    for (const lbm_launch &c : candidates(lat->v)) {
+        double us;
+        lbm_status st = time_shape(lat, c, reps, &us);
+        if (st != LBM_OK) return st;
+        if (us < best_t) {
+            best_t = us;
+            best_c = c;
+        }
+    }
+    lat->launch = best_c;
+    if (best) *best = best_c;
+    if (best_us) *best_us = best_t;
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+"""GPU invariants that hold at any size, checked bitwise where the arithmetic
+is identical: translation, y-uniformity, checkpoint/resume, launch shapes,
+tuning leaves the state alone, conservation, and failure reporting."""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs
+from oracle import linear
+
+pytestmark = pytest.mark.gpu
+
+LL = lbm_inputs.PRESETS["LL"]
+
+
+def ll_rates(nu=1e-3):
+    return [LL["s_e"], LL["s_eps"], LL["s_q"], float(linear.s_from_nu(nu))]
+
+
+def lattice(nx, ny, s, storage="f32", u0=(0.0, 0.0), **kw):
+    from paper_1107_4543_amd import Lattice
+    return Lattice(nx, ny, *s, storage=storage, u0=u0, device="cuda:0", **kw)
+
+
+def fields(nx, ny, seed, u0=(0.0, 0.0)):
+    rng = np.random.default_rng(seed)
+    return (1.0 + 1e-3 * rng.standard_normal((ny, nx)), u0[0] + 1e-3 * rng.standard_normal((ny, nx)),
+            u0[1] + 1e-3 * rng.standard_normal((ny, nx)))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_translation_invariance_bitwise(storage):
+    nx, ny = 128, 96
+    rho, ux, uy = fields(nx, ny, 1)
+    s = ll_rates()
+    a = lattice(nx, ny, s, storage, scale_exp=20 if storage == "f16" else None).init(rho, ux, uy).step(37)
+    sh = (5, -9)
+    b = lattice(nx, ny, s, storage, scale_exp=20 if storage == "f16" else None)
+    b.init(*(np.roll(f, sh, axis=(0, 1)) for f in (rho, ux, uy))).step(37)
+    ra = torch.roll(a.populations(), sh, dims=(1, 2))
+    assert torch.equal(ra, b.populations())
+
+
+def test_y_uniform_stays_bitwise_and_large_equals_single_row():
+    nx = 1024
+    s = [1.99, 1.962820428, 1.992761413, 1.999960001]
+    rho, ux, uy = lbm_inputs.plane_waves(nx, 1, 3, 1e-4, 1e-4, 0.0577)
+    big = lattice(nx, 256, s, u0=(0.0577, 0.0))
+    big.init(*(np.broadcast_to(a, (256, nx)).copy() for a in (rho, ux, uy))).step(100)
+    one = lattice(nx, 1, s, u0=(0.0577, 0.0)).init(rho, ux, uy).step(100)
+    fb = big.populations()
+    assert torch.equal(fb, fb[:, :1].expand_as(fb))
+    assert torch.equal(fb[:, :1], one.populations())
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_checkpoint_resume_is_bitwise(storage):
+    nx, ny = 96, 80
+    rho, ux, uy = fields(nx, ny, 2, (0.03, 0.0))
+    s = ll_rates()
+    a = lattice(nx, ny, s, storage, u0=(0.03, 0.0)).init(rho, ux, uy).step(60)
+    b = lattice(nx, ny, s, storage, u0=(0.03, 0.0)).init(rho, ux, uy).step(30)
+    buf, t = b.save_state()
+    c = lattice(nx, ny, s, storage, u0=(0.03, 0.0), scale_exp=b.scale_exp).load_state(buf.clone(), t)
+    assert c.t == 30
+    c.step(30)
+    assert torch.equal(a.populations(), c.populations())
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_all_launch_shapes_give_identical_results(storage):
+    nx, ny = 256, 72
+    rho, ux, uy = fields(nx, ny, 3, (0.02, 0.01))
+    s = ll_rates()
+    ref = None
+    for launch in [dict(variant=0, block_x=64, block_y=4, rows=1, xcd_remap=1),
+                   dict(variant=0, block_x=256, block_y=1, rows=3, xcd_remap=0),
+                   dict(variant=1, block_x=64, block_y=1, rows=1, xcd_remap=0),
+                   dict(variant=2, block_x=128, block_y=2, rows=2, xcd_remap=1),
+                   dict(variant=3, block_x=64, block_y=4, rows=4, xcd_remap=1)]:
+        lat = lattice(nx, ny, s, storage, u0=(0.02, 0.01))
+        lat.set_launch(**launch)
+        f = lat.init(rho, ux, uy).step(25).populations()
+        if ref is None:
+            ref = f
+        else:
+            assert torch.equal(ref, f), launch
+
+
+def test_tune_and_timing_leave_the_state_unchanged():
+    nx, ny = 512, 128
+    rho, ux, uy = fields(nx, ny, 4)
+    s = ll_rates()
+    a = lattice(nx, ny, s).init(rho, ux, uy).step(5)
+    before = a.populations().clone()
+    cfg, us = a.tune(reps=2)
+    assert us > 0 and cfg["block_x"] >= 64
+    a.time_launches(3)
+    assert a.t == 5
+    assert torch.equal(before, a.populations())
+    a.step(4)
+    b = lattice(nx, ny, s).init(rho, ux, uy).step(9)
+    assert torch.equal(a.populations(), b.populations())
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_mass_and_momentum_are_conserved(storage):
+    nx, ny, A = 256, 256, 1e-3
+    rho, ux, uy = lbm_inputs.gaussian_pulse(nx, ny, A, 8.0, u0=(0.04, 0.0))
+    lat = lattice(nx, ny, ll_rates(), storage, u0=(0.04, 0.0)).init(rho, ux, uy)
+    st0, d0 = lat.diagnostics()
+    lat.step(500)
+    st1, d1 = lat.diagnostics()
+    assert st0 == 0 and st1 == 0 and d1[3] == 0
+    # FP64 sum of the initial mass excess: sum A exp(-ln2 d^2/b^2) = A pi b^2 / ln 2
+    assert abs(d0[0] - A * np.pi * 64 / np.log(2)) < 1e-6 * d0[0]
+    unit = 2.2e-16 if storage == "f64" else 1.2e-7
+    tol = 10 * unit * A * np.sqrt(nx * ny * 500)      # random walk of storage rounding
+    for k in range(3):
+        assert abs(d1[k] - d0[k]) <= tol, (k, d0, d1)
+
+
+def test_non_finite_input_is_reported():
+    from paper_1107_4543_amd import _lib
+    nx, ny = 64, 64
+    rho, ux, uy = fields(nx, ny, 6)
+    rho[10, 20] = np.nan
+    lat = lattice(nx, ny, ll_rates()).init(rho, ux, uy)
+    st, d = lat.diagnostics()
+    assert st == _lib.LBM_E_NONFINITE and d[3] >= 1
+    lat.step(3)
+    st, d = lat.diagnostics()
+    assert st == _lib.LBM_E_NONFINITE and d[3] > 9
+
+
+def test_unstable_relaxation_set_blows_up_and_is_flagged():
+    # A set outside the linear stability region (max |lambda| > 1 at the
+    # checkerboard mode) must end in non-finite values that the diagnostics
+    # report; the von Neumann screen predicts it.
+    s = [1.860, 1.075, 1.312, 1.9169]
+    assert linear.spectral_radius(*s, nk=16) > 1.0
+    nx = ny = 64
+    rho, ux, uy = lbm_inputs.gaussian_pulse(nx, ny, 1e-3, 4.0)
+    lat = lattice(nx, ny, s, "f64").init(rho, ux, uy).step(1000)
+    st, d = lat.diagnostics()
+    from paper_1107_4543_amd import _lib
+    assert st == _lib.LBM_E_NONFINITE
