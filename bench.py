@@ -104,6 +104,34 @@ def cpu_baseline(rates, fields1, nx, ny, u0x, budget_s):
                       f"{steps} step(s), {elapsed:.1f} s"}
 
 
+def copy_probe(nbytes, reps):
+    """Plain device-to-device copy of nbytes, reps times (the calibration
+    kernel for the HBM byte counters and the achievable-bandwidth context)."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / reps
+    return {"bytes_per_copy": nbytes, "us_per_copy": round(us, 2),
+            "GBps": round(2 * nbytes / (us * 1e-6) / 1e9, 1)}
+
+
+def parse_launch(text):
+    keys = ["variant", "block_x", "block_y", "rows", "xcd_remap", "flags"]
+    vals = [int(v) for v in text.split(",")]
+    if len(vals) != len(keys):
+        raise SystemExit("--launch takes variant,block_x,block_y,rows,xcd_remap,flags")
+    return dict(zip(keys, vals))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +139,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16", "bf16"])
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--launch", default=None,
+                    help="fixed launch shape variant,block_x,block_y,rows,xcd_remap,flags (no tuning)")
+    ap.add_argument("--probe", choices=["copy"], default=None,
+                    help="run only the device-to-device copy probe")
+    ap.add_argument("--probe-bytes", type=int, default=1 << 30)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work (0 = skip)")
     args = ap.parse_args()
 
@@ -123,10 +156,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.init()
 
+    if args.probe == "copy":
+        print(json.dumps({"probe": "copy", **copy_probe(args.probe_bytes, args.steps)}), flush=True)
+        return
+
     lat, cfg, rates, fields1, w = build_waves4096(args.storage)
-    tuned = None
-    if not args.no_tune:
-        tuned, _ = lat.tune(reps=5)
+    if args.launch:
+        lat.set_launch(**parse_launch(args.launch))
+    elif not args.no_tune:
+        lat.tune(reps=5)
     cfg["launch"] = lat.launch
 
     stream = lat.stream
@@ -160,6 +198,7 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_launch_us": round(us_per_launch, 3)},
     }
+    out["context"] = {"copy_probe": copy_probe(alg_bytes // 2, 10), "device": torch.cuda.get_device_name(0)}
     if args.cpu_budget > 0:
         out["cpu_baseline"] = cpu_baseline(rates, fields1, lat.nx, lat.ny, w["u0x"], args.cpu_budget)
     print(json.dumps(out), flush=True)

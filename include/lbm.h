@@ -99,20 +99,25 @@ typedef struct lbm_desc {
 typedef struct lbm_lattice lbm_lattice;
 
 /* Launch shape of the fused step kernel (chosen by lbm_tune or set by hand).
- *   variant   0 = one cell per lane, 1 = two cells per lane (x pairs),
- *             2 = four cells per lane (x quads)
- *   block_x   lanes along x per workgroup (multiple of 64 over the lanes)
- *   block_y   rows per workgroup pass
- *   rows      rows each lane processes (tile height = block_y * rows)
- *   xcd_remap 1 = remap workgroup ids so that neighbouring tiles run on the
- *             same XCD (shared L2), 0 = hardware order. */
+ *   variant   0 = one cell per lane (nine direct loads),
+ *             1, 2, 3 = 2, 4, 8 consecutive cells per lane (aligned vector
+ *             loads, x-shift by cross-lane exchange; needs nx % 2^variant == 0
+ *             and block_x % 64 == 0)
+ *   block_x   lanes along x per workgroup, block_y rows per workgroup pass;
+ *             64 <= block_x * block_y <= 1024
+ *   rows      rows each lane processes, 1..64 (tile height = block_y * rows)
+ *   xcd_remap 1 = renumber workgroups so that neighbouring tiles run on the
+ *             same XCD (shared L2), 0 = hardware order
+ *   flags     bit 0: non-temporal loads; bit 1: issue the next row's loads
+ *             before colliding the current row (variant 0 only).
+ * Every shape produces bit-identical results. */
 typedef struct lbm_launch {
     int32_t variant;
     int32_t block_x;
     int32_t block_y;
     int32_t rows;
     int32_t xcd_remap;
-    int32_t reserved;
+    int32_t flags;
 } lbm_launch;
 
 /* ---- status and helpers ------------------------------------------------ */

@@ -42,10 +42,10 @@ class lbm_desc(ctypes.Structure):
 class lbm_launch(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("block_x", ctypes.c_int32),
                 ("block_y", ctypes.c_int32), ("rows", ctypes.c_int32),
-                ("xcd_remap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("xcd_remap", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 _lib = None

@@ -108,28 +108,41 @@ lbm_launch default_launch(const View &)
     return c;
 }
 
-// Candidate shapes for the tuner.
-std::vector<lbm_launch> candidates(const View &v)
+// Tuner stage 1: workgroup shapes of the one-cell kernel.
+std::vector<lbm_launch> shape_candidates(const View &v)
 {
     std::vector<lbm_launch> out;
-    const int variants[] = {0, 1, 2, 3};
-    const int bxs[] = {64, 128, 256};
-    const int bys[] = {1, 2, 4};
-    const int rows[] = {1, 2, 4};
-    for (int var : variants)
-        for (int bx : bxs)
-            for (int by : bys)
-                for (int r : rows)
-                    for (int remap = 0; remap < 2; ++remap) {
-                        if (bx * by > 512) continue;
-                        lbm_launch c{};
-                        c.variant = var;
-                        c.block_x = bx;
-                        c.block_y = by;
-                        c.rows = r;
-                        c.xcd_remap = remap;
-                        if (lbm::step_shape_supported(v, c)) out.push_back(c);
-                    }
+    const int shapes[][2] = {{64, 1}, {64, 2}, {64, 4}, {64, 8}, {128, 1}, {128, 2}, {128, 4},
+                             {256, 1}, {256, 2}, {256, 4}, {512, 1}, {512, 2}, {1024, 1}};
+    for (const auto &sh : shapes)
+        for (int r : {1, 2, 4})
+            for (int remap = 0; remap < 2; ++remap) {
+                lbm_launch c{};
+                c.variant = 0;
+                c.block_x = sh[0];
+                c.block_y = sh[1];
+                c.rows = r;
+                c.xcd_remap = remap;
+                c.flags = 0;
+                if (lbm::step_shape_supported(v, c)) out.push_back(c);
+            }
+    return out;
+}
+
+// Tuner stage 2: kernel variants and flags around the best shape.
+std::vector<lbm_launch> variant_candidates(const View &v, const lbm_launch &best)
+{
+    std::vector<lbm_launch> out;
+    for (int var = 0; var < 4; ++var)
+        for (int flags = 0; flags < 4; ++flags)
+            for (int rows : {best.rows, 2 * best.rows}) {
+                lbm_launch c = best;
+                c.variant = var;
+                c.flags = flags;
+                c.rows = rows;
+                if (var > 0 && c.block_x % 64 != 0) c.block_x = 64 * ((c.block_x + 63) / 64);
+                if (lbm::step_shape_supported(v, c)) out.push_back(c);
+            }
     return out;
 }
 
@@ -419,15 +432,21 @@ lbm_status lbm_tune(lbm_lattice *lat, int32_t reps, lbm_launch *best, double *be
     if (!lat->initialized) return fail(LBM_E_STATE, "tune before init");
     double best_t = INFINITY;
     lbm_launch best_c = lat->launch;
-    for (const lbm_launch &c : candidates(lat->v)) {
-        double us;
-        lbm_status st = time_shape(lat, c, reps, &us);
-        if (st != LBM_OK) return st;
-        if (us < best_t) {
-            best_t = us;
-            best_c = c;
+    auto sweep = [&](const std::vector<lbm_launch> &cands) -> lbm_status {
+        for (const lbm_launch &c : cands) {
+            double us;
+            lbm_status st = time_shape(lat, c, reps, &us);
+            if (st != LBM_OK) return st;
+            if (us < best_t) {
+                best_t = us;
+                best_c = c;
+            }
         }
-    }
+        return LBM_OK;
+    };
+    lbm_status st = sweep(shape_candidates(lat->v));
+    if (st == LBM_OK) st = sweep(variant_candidates(lat->v, best_c));
+    if (st != LBM_OK) return st;
     lat->launch = best_c;
     if (best) *best = best_c;
     if (best_us) *best_us = best_t;

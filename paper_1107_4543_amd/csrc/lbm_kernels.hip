@@ -82,12 +82,23 @@ __device__ __forceinline__ void cell_update(typename Store<S>::wide w[9], const 
 
 // ---- fused step -------------------------------------------------------------
 
+template <typename S, bool NT>
+__device__ __forceinline__ typename Store<S>::wide ld(const typename Store<S>::raw *p)
+{
+    if constexpr (NT) return Store<S>::widen(__builtin_nontemporal_load(p));
+    else return Store<S>::widen(*p);
+}
+
 // One cell per lane: nine direct (possibly misaligned) loads.
-template <typename S, typename C>
+// FLAGS bit 0: non-temporal loads; bit 1: the nine loads of the lane's next
+// row are issued before the current row is collided and stored.
+template <typename S, typename C, int FLAGS>
 __global__ void __launch_bounds__(1024) k_step_v1(StepArgs<C> a)
 {
     using R = typename Store<S>::raw;
     using W = typename Store<S>::wide;
+    constexpr bool NT = (FLAGS & 1) != 0;
+    constexpr bool PIPE = (FLAGS & 2) != 0;
     int bid = blockIdx.x;
     if (a.xcd_remap) bid = remap_xcd(bid, a.nblocks);
     const int tile_x = bid % a.tiles_x, tile_y = bid / a.tiles_x;
@@ -98,25 +109,43 @@ __global__ void __launch_bounds__(1024) k_step_v1(StepArgs<C> a)
     const R *__restrict__ src = (const R *)a.src;
     R *__restrict__ dst = (R *)a.dst;
     const int64_t P = a.plane;
-    int y = tile_y * a.tile_h + threadIdx.y;
-    for (int rr = 0; rr < a.rows; ++rr, y += blockDim.y) {
-        if (y >= a.ny) return;
+    auto gather = [&](int y, W w[9]) {
         const int ym = (y == 0 ? a.ny : y) - 1;
         const int yp = (y + 1 == a.ny) ? 0 : y + 1;
         const int64_t r0 = (int64_t)y * a.pitch, rm = (int64_t)ym * a.pitch, rp = (int64_t)yp * a.pitch;
-        W w[9];
-        w[0] = Store<S>::widen(src[0 * P + r0 + x]);
-        w[1] = Store<S>::widen(src[1 * P + r0 + xm]);
-        w[2] = Store<S>::widen(src[2 * P + rm + x]);
-        w[3] = Store<S>::widen(src[3 * P + r0 + xp]);
-        w[4] = Store<S>::widen(src[4 * P + rp + x]);
-        w[5] = Store<S>::widen(src[5 * P + rm + xm]);
-        w[6] = Store<S>::widen(src[6 * P + rm + xp]);
-        w[7] = Store<S>::widen(src[7 * P + rp + xp]);
-        w[8] = Store<S>::widen(src[8 * P + rp + xm]);
+        w[0] = ld<S, NT>(src + 0 * P + r0 + x);
+        w[1] = ld<S, NT>(src + 1 * P + r0 + xm);
+        w[2] = ld<S, NT>(src + 2 * P + rm + x);
+        w[3] = ld<S, NT>(src + 3 * P + r0 + xp);
+        w[4] = ld<S, NT>(src + 4 * P + rp + x);
+        w[5] = ld<S, NT>(src + 5 * P + rm + xm);
+        w[6] = ld<S, NT>(src + 6 * P + rm + xp);
+        w[7] = ld<S, NT>(src + 7 * P + rp + xp);
+        w[8] = ld<S, NT>(src + 8 * P + rp + xm);
+    };
+    int y = tile_y * a.tile_h + threadIdx.y;
+    if (y >= a.ny) return;
+    W w[9];
+    gather(y, w);
+    for (int rr = 0; rr < a.rows; ++rr) {
+        const int yn = y + blockDim.y;
+        const bool more = rr + 1 < a.rows && yn < a.ny;
+        W nxt[9];
+        if constexpr (PIPE) {
+            if (more) gather(yn, nxt);
+        }
         cell_update<S, C>(w, a.r, a.scale, a.inv_scale);
+        const int64_t r0 = (int64_t)y * a.pitch;
 #pragma unroll
         for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(Store<S>::narrow(w[i]), dst + i * P + r0 + x);
+        if (!more) return;
+        if constexpr (PIPE) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) w[i] = nxt[i];
+        } else {
+            gather(yn, w);
+        }
+        y = yn;
     }
 }
 
@@ -124,9 +153,10 @@ __global__ void __launch_bounds__(1024) k_step_v1(StepArgs<C> a)
 // x-shift of populations with v_x = +-1 is taken from the neighbouring lane
 // (cross-lane shuffle), and only the first / last lane of a wave loads its
 // edge element directly.  Needs nx % VX == 0 and blockDim.x % 64 == 0.
-template <typename S, typename C, int VX>
+template <typename S, typename C, int VX, int FLAGS>
 __global__ void __launch_bounds__(1024) k_step_vec(StepArgs<C> a)
 {
+    constexpr bool NT = (FLAGS & 1) != 0;
     using R = typename Store<S>::raw;
     using W = typename Store<S>::wide;
     using V = typename VecOf<R, VX>::type;
@@ -157,7 +187,9 @@ __global__ void __launch_bounds__(1024) k_step_vec(StepArgs<C> a)
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const R *row = src + i * P + rowoff[ROW[i]];
-            const V raw = *(const V *)(row + x0);
+            V raw;
+            if constexpr (NT) raw = __builtin_nontemporal_load((const V *)(row + x0));
+            else raw = *(const V *)(row + x0);
             W vals[VX];
 #pragma unroll
             for (int k = 0; k < VX; ++k) {
@@ -502,11 +534,18 @@ hipError_t launch_step_typed(const View &v, const void *src, void *dst, const lb
     a.scale = (float)v.scale;
     a.inv_scale = (float)v.inv_scale;
     const dim3 grid(a.nblocks), block(cfg.block_x, cfg.block_y);
-    switch (cfg.variant) {
-    case 0: hipLaunchKernelGGL((k_step_v1<S, C>), grid, block, 0, st, a); break;
-    case 1: hipLaunchKernelGGL((k_step_vec<S, C, 2>), grid, block, 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_step_vec<S, C, 4>), grid, block, 0, st, a); break;
-    case 3: hipLaunchKernelGGL((k_step_vec<S, C, 8>), grid, block, 0, st, a); break;
+    const bool nt = cfg.flags & 1, pipe = cfg.flags & 2;
+    switch (cfg.variant * 4 + (pipe ? 2 : 0) + (nt ? 1 : 0)) {
+    case 0: hipLaunchKernelGGL((k_step_v1<S, C, 0>), grid, block, 0, st, a); break;
+    case 1: hipLaunchKernelGGL((k_step_v1<S, C, 1>), grid, block, 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_step_v1<S, C, 2>), grid, block, 0, st, a); break;
+    case 3: hipLaunchKernelGGL((k_step_v1<S, C, 3>), grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_step_vec<S, C, 2, 0>), grid, block, 0, st, a); break;
+    case 5: hipLaunchKernelGGL((k_step_vec<S, C, 2, 1>), grid, block, 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_step_vec<S, C, 4, 0>), grid, block, 0, st, a); break;
+    case 9: hipLaunchKernelGGL((k_step_vec<S, C, 4, 1>), grid, block, 0, st, a); break;
+    case 12: hipLaunchKernelGGL((k_step_vec<S, C, 8, 0>), grid, block, 0, st, a); break;
+    case 13: hipLaunchKernelGGL((k_step_vec<S, C, 8, 1>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -610,6 +649,8 @@ bool step_shape_supported(const View &v, const lbm_launch &cfg)
     if (cfg.block_x * cfg.block_y > 1024 || cfg.block_x * cfg.block_y < 64) return false;
     if (cfg.block_x % 64 != 0 && cfg.block_x * cfg.block_y % 64 != 0) return false;
     if (cfg.xcd_remap != 0 && cfg.xcd_remap != 1) return false;
+    if (cfg.flags < 0 || cfg.flags > 3) return false;
+    if ((cfg.flags & 2) && cfg.variant != 0) return false;     // row pipelining: one-cell kernel only
     if (cfg.variant > 0) {
         const int vx = 1 << cfg.variant;
         if (cfg.block_x % 64 != 0 || v.nx % vx != 0) return false;

@@ -138,8 +138,8 @@ class Lattice:
     def launch(self):
         return _lib.lbm_get_launch(self._h).as_dict()
 
-    def set_launch(self, variant=0, block_x=64, block_y=4, rows=1, xcd_remap=1):
-        c = _lib.lbm_launch(variant, block_x, block_y, rows, xcd_remap, 0)
+    def set_launch(self, variant=0, block_x=64, block_y=4, rows=1, xcd_remap=1, flags=0):
+        c = _lib.lbm_launch(variant, block_x, block_y, rows, xcd_remap, flags)
         _lib.lbm_set_launch(self._h, c)
         return self
 

@@ -183,13 +183,19 @@ def test_projection_matches_numpy_fourier_sum():
     rho = 1.0 + 1e-3 * rng.standard_normal((ny, nx))
     ux = 0.01 + 1e-3 * rng.standard_normal((ny, nx))
     uy = 1e-3 * rng.standard_normal((ny, nx))
-    lat = lattice(nx, ny, ll_rates(), u0=(0.01, 0.0)).init(rho, ux, uy).step(7)
+    s = ll_rates()
+    lat = lattice(nx, ny, s, u0=(0.01, 0.0)).init(rho, ux, uy).step(7)
     f = np_(lat.populations())
-    base = oracle.init(np.ones((1, 1)), np.full((1, 1), 0.01), np.zeros((1, 1)))[:, 0, 0]
+    # the library's own base state, read back from a uniform lattice (g = 0)
+    uni = lattice(1, 1, s, u0=(0.01, 0.0)).init(np.ones((1, 1)), np.full((1, 1), 0.01), np.zeros((1, 1)))
+    base = np_(uni.populations())[:, 0, 0]
     X, Y = np.meshgrid(np.arange(nx), np.arange(ny))
+    # each read-back f = base + g carries one rounding of size ulp(f)/2
+    tol_abs = nx * ny * np.spacing(np.max(np.abs(f)))
     for mx, my in [(0, 0), (3, 0), (5, -2), (-7, 11), (95, 39)]:
-        ph = np.exp(-2j * np.pi * (mx * X / nx + my * Y / ny))
+        frac = ((mx * X) % nx) / nx + ((my * Y) % ny) / ny          # exact phase reduction
+        ph = np.exp(-2j * np.pi * frac)
         want = ((f - base[:, None, None]) * ph[None]).sum(axis=(1, 2))
         got = np_(lat.project(mx, my))
         got = got[0::2] + 1j * got[1::2]
-        assert np.max(np.abs(got - want)) <= 1e-12 * max(1e-12, np.max(np.abs(want))) + 1e-17 * nx * ny
+        assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want)) + tol_abs, (mx, my)
