@@ -102,14 +102,17 @@ typedef struct lbm_lattice lbm_lattice;
  *   variant   0 = one cell per lane (nine direct loads),
  *             1, 2, 3 = 2, 4, 8 consecutive cells per lane (aligned vector
  *             loads, x-shift by cross-lane exchange; needs nx % 2^variant == 0
- *             and block_x % 64 == 0)
+ *             and block_x % 64 == 0),
+ *             4 = one cell per lane, each workgroup walks whole rows in chunks
+ *             of block_x cells (row strips)
  *   block_x   lanes along x per workgroup, block_y rows per workgroup pass;
  *             64 <= block_x * block_y <= 1024
  *   rows      rows each lane processes, 1..64 (tile height = block_y * rows)
  *   xcd_remap 1 = renumber workgroups so that neighbouring tiles run on the
  *             same XCD (shared L2), 0 = hardware order
- *   flags     bit 0: non-temporal loads; bit 1: issue the next row's loads
- *             before colliding the current row (variant 0 only).
+ *   flags     bit 0: non-temporal loads; bit 1: issue the next row's (variant
+ *             0) or next chunk's (variant 4) loads before colliding the current
+ *             cells.
  * Every shape produces bit-identical results. */
 typedef struct lbm_launch {
     int32_t variant;
@@ -212,6 +215,74 @@ LBM_API lbm_status lbm_set_launch(lbm_lattice *lat, const lbm_launch *cfg);
 LBM_API lbm_status lbm_tune(lbm_lattice *lat, int32_t reps, lbm_launch *best, double *best_us);
 /* Times n launches of the current shape (state unchanged; syncs). */
 LBM_API lbm_status lbm_time_launches(lbm_lattice *lat, int32_t n, double *avg_us);
+
+/* ---- pools: many lattices advanced together ------------------------------
+ *
+ * A pool advances its members (lattices of any size, rates and storage)
+ * with one persistent launch per storage class and step; the step loop is
+ * recorded once as a HIP graph of graph_steps steps and replayed.  Each
+ * member carries its own step count: a member added with nsteps stops after
+ * exactly nsteps steps, independently of the others, and is then returned by
+ * lbm_pool_poll.  Members join and leave between lbm_pool_step calls
+ * (continuous batching).  A lattice gives bit-identical results alone or in
+ * a pool (same per-cell arithmetic).
+ *
+ * While a lattice is in a pool, every lattice call that reads or changes its
+ * state returns LBM_E_STATE.  Ordering: lbm_pool_add makes the pool's stream
+ * wait for work already enqueued on the lattice's stream; lbm_pool_poll and
+ * lbm_pool_remove make the lattice's stream wait for the pool's stream, so
+ * readback enqueued afterwards on the lattice's stream sees the final state. */
+
+typedef struct lbm_pool lbm_pool;
+
+/* Launch shape of a pool.
+ *   tile_cells   target cells per tile (a tile is whole rows of one member:
+ *                max(1, tile_cells / nx) rows), 64 .. 2^22
+ *   block        threads per workgroup, multiple of 64, 64 .. 1024
+ *   grid         workgroups of the persistent launch, 1 .. 2^20
+ *   graph_steps  steps recorded in one graph replay, 1 .. 1024 */
+typedef struct lbm_pool_shape {
+    int32_t tile_cells;
+    int32_t block;
+    int32_t grid;
+    int32_t graph_steps;
+} lbm_pool_shape;
+
+/* Device bytes of a pool's member and tile tables; 0 if out of range
+ * (max_members in [1, 2^20], max_tiles in [1, 2^26]). */
+LBM_API size_t lbm_pool_workspace_bytes(int32_t max_members, int32_t max_tiles);
+/* Creates a pool.  dev_ws: device pointer, 256-byte aligned, at least
+ * lbm_pool_workspace_bytes bytes, owned by the caller; stream: the pool's
+ * hipStream_t.  Allocates pinned host staging for the tables. */
+LBM_API lbm_status lbm_pool_create(void *dev_ws, size_t ws_bytes, void *stream, int32_t max_members,
+                                   int32_t max_tiles, lbm_pool **out);
+/* Returns every member to its lattice (as lbm_pool_remove) and frees the
+ * handle; does not free dev_ws. */
+LBM_API lbm_status lbm_pool_destroy(lbm_pool *pool);
+/* Adds an initialised lattice that will advance nsteps >= 0 more steps.
+ * LBM_E_NOMEM when the member or tile table is full. */
+LBM_API lbm_status lbm_pool_add(lbm_pool *pool, lbm_lattice *lat, int64_t nsteps);
+/* Takes a member out before it is done; its time is the steps taken so far. */
+LBM_API lbm_status lbm_pool_remove(lbm_pool *pool, lbm_lattice *lat);
+/* Advances every member by min(nsteps, its remaining steps).  Enqueued. */
+LBM_API lbm_status lbm_pool_step(lbm_pool *pool, int64_t nsteps);
+/* Returns up to cap members whose steps are done and whose last step has
+ * completed on the device; they leave the pool.  wait != 0 blocks until at
+ * least the oldest finished member has completed (if there is one). */
+LBM_API lbm_status lbm_pool_poll(lbm_pool *pool, lbm_lattice **done, int32_t cap, int32_t wait,
+                                 int32_t *ndone);
+/* Members currently held (including finished ones not yet polled). */
+LBM_API int32_t lbm_pool_members(const lbm_pool *pool);
+/* Steps a member still has to take, or -1 if it is not in the pool. */
+LBM_API int64_t lbm_pool_remaining(const lbm_pool *pool, const lbm_lattice *lat);
+LBM_API lbm_status lbm_pool_get_shape(const lbm_pool *pool, lbm_pool_shape *out);
+/* LBM_E_INVAL for an invalid shape, LBM_E_NOMEM if the tiles would not fit. */
+LBM_API lbm_status lbm_pool_set_shape(lbm_pool *pool, const lbm_pool_shape *shape);
+/* Times reps launches of one step of every member (states unchanged; syncs). */
+LBM_API lbm_status lbm_pool_time_launches(lbm_pool *pool, int32_t reps, double *avg_us);
+/* Times tile sizes, workgroup sizes and grid sizes on the current members,
+ * keeps the fastest (states unchanged; syncs). */
+LBM_API lbm_status lbm_pool_tune(lbm_pool *pool, int32_t reps, lbm_pool_shape *best, double *best_us);
 
 #ifdef __cplusplus
 }

@@ -48,6 +48,14 @@ class lbm_launch(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class lbm_pool_shape(ctypes.Structure):
+    _fields_ = [("tile_cells", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("graph_steps", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -78,6 +86,20 @@ SIGNATURES = {
     "lbm_set_launch": (_st, [_vp, ctypes.POINTER(lbm_launch)]),
     "lbm_tune": (_st, [_vp, ctypes.c_int32, ctypes.POINTER(lbm_launch), _dp]),
     "lbm_time_launches": (_st, [_vp, ctypes.c_int32, _dp]),
+    "lbm_pool_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "lbm_pool_create": (_st, [_vp, ctypes.c_size_t, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_vp)]),
+    "lbm_pool_destroy": (_st, [_vp]),
+    "lbm_pool_add": (_st, [_vp, _vp, ctypes.c_int64]),
+    "lbm_pool_remove": (_st, [_vp, _vp]),
+    "lbm_pool_step": (_st, [_vp, ctypes.c_int64]),
+    "lbm_pool_poll": (_st, [_vp, ctypes.POINTER(_vp), ctypes.c_int32, ctypes.c_int32,
+                            ctypes.POINTER(ctypes.c_int32)]),
+    "lbm_pool_members": (ctypes.c_int32, [_vp]),
+    "lbm_pool_remaining": (ctypes.c_int64, [_vp, _vp]),
+    "lbm_pool_get_shape": (_st, [_vp, ctypes.POINTER(lbm_pool_shape)]),
+    "lbm_pool_set_shape": (_st, [_vp, ctypes.POINTER(lbm_pool_shape)]),
+    "lbm_pool_time_launches": (_st, [_vp, ctypes.c_int32, _dp]),
+    "lbm_pool_tune": (_st, [_vp, ctypes.c_int32, ctypes.POINTER(lbm_pool_shape), _dp]),
 }
 
 
@@ -213,3 +235,71 @@ def lbm_time_launches(h, n):
     us = ctypes.c_double()
     check(load().lbm_time_launches(h, int(n), ctypes.byref(us)), "lbm_time_launches")
     return us.value
+
+
+# ---- pools ----------------------------------------------------------------------
+
+def lbm_pool_workspace_bytes(max_members, max_tiles):
+    return int(load().lbm_pool_workspace_bytes(int(max_members), int(max_tiles)))
+
+
+def lbm_pool_create(dev_ws, ws_bytes, stream, max_members, max_tiles):
+    h = _vp()
+    check(load().lbm_pool_create(_vp(dev_ws), ws_bytes, _vp(stream), int(max_members), int(max_tiles),
+                                 ctypes.byref(h)), "lbm_pool_create")
+    return h
+
+
+def lbm_pool_destroy(p):
+    check(load().lbm_pool_destroy(p), "lbm_pool_destroy")
+
+
+def lbm_pool_add(p, lat, nsteps):
+    check(load().lbm_pool_add(p, lat, int(nsteps)), "lbm_pool_add")
+
+
+def lbm_pool_remove(p, lat):
+    check(load().lbm_pool_remove(p, lat), "lbm_pool_remove")
+
+
+def lbm_pool_step(p, nsteps):
+    check(load().lbm_pool_step(p, int(nsteps)), "lbm_pool_step")
+
+
+def lbm_pool_poll(p, cap, wait=False):
+    """Returns the list of finished lattice handles (as integers)."""
+    arr = (_vp * max(1, cap))()
+    n = ctypes.c_int32()
+    check(load().lbm_pool_poll(p, arr, int(cap), 1 if wait else 0, ctypes.byref(n)), "lbm_pool_poll")
+    return [arr[i] for i in range(n.value)]
+
+
+def lbm_pool_members(p):
+    return int(load().lbm_pool_members(p))
+
+
+def lbm_pool_remaining(p, lat):
+    return int(load().lbm_pool_remaining(p, lat))
+
+
+def lbm_pool_get_shape(p):
+    s = lbm_pool_shape()
+    check(load().lbm_pool_get_shape(p, ctypes.byref(s)), "lbm_pool_get_shape")
+    return s
+
+
+def lbm_pool_set_shape(p, shape):
+    check(load().lbm_pool_set_shape(p, ctypes.byref(shape)), "lbm_pool_set_shape")
+
+
+def lbm_pool_time_launches(p, reps):
+    us = ctypes.c_double()
+    check(load().lbm_pool_time_launches(p, int(reps), ctypes.byref(us)), "lbm_pool_time_launches")
+    return us.value
+
+
+def lbm_pool_tune(p, reps):
+    s = lbm_pool_shape()
+    us = ctypes.c_double()
+    check(load().lbm_pool_tune(p, int(reps), ctypes.byref(s), ctypes.byref(us)), "lbm_pool_tune")
+    return s, us.value

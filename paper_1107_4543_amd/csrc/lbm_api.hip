@@ -18,23 +18,6 @@
 
 using lbm::View;
 
-struct lbm_lattice {
-    View v;
-    lbm_desc desc;
-    char *ws = nullptr;
-    size_t ws_bytes = 0;
-    size_t buf_bytes = 0;      // bytes of one buffer (aligned)
-    size_t state_bytes = 0;    // bytes of one buffer's planes (exact)
-    void *buf[2] = {nullptr, nullptr};
-    int cur = 0;
-    double *partials = nullptr;
-    double *result = nullptr;
-    hipStream_t stream = nullptr;
-    int64_t t = 0;
-    bool initialized = false;
-    lbm_launch launch{};
-};
-
 namespace {
 
 thread_local std::string g_err;
@@ -48,6 +31,11 @@ lbm_status fail(lbm_status s, const char *fmt, ...)
     va_end(ap);
     g_err = buf;
     return s;
+}
+
+lbm_status busy(const lbm_lattice *L)
+{
+    return fail(LBM_E_STATE, "lattice is being advanced by a pool (remove it or poll it first)");
 }
 
 lbm_status hip_fail(hipError_t e, const char *what)
@@ -133,7 +121,7 @@ std::vector<lbm_launch> shape_candidates(const View &v)
 std::vector<lbm_launch> variant_candidates(const View &v, const lbm_launch &best)
 {
     std::vector<lbm_launch> out;
-    for (int var = 0; var < 4; ++var)
+    for (int var = 0; var < 5; ++var)
         for (int flags = 0; flags < 4; ++flags)
             for (int rows : {best.rows, 2 * best.rows}) {
                 lbm_launch c = best;
@@ -176,6 +164,8 @@ lbm_status time_shape(lbm_lattice *L, const lbm_launch &c, int reps, double *us)
 }
 
 }  // namespace
+
+void lbm::set_error_text(const char *msg) { g_err = msg; }
 
 extern "C" {
 
@@ -260,6 +250,7 @@ lbm_status lbm_create(const lbm_desc *desc, void *dev_ws, size_t ws_bytes, void 
 lbm_status lbm_destroy(lbm_lattice *lat)
 {
     if (!lat) return fail(LBM_E_INVAL, "lattice is NULL");
+    if (lat->pool) return busy(lat);
     delete lat;
     return LBM_OK;
 }
@@ -282,6 +273,7 @@ lbm_status lbm_get_desc(const lbm_lattice *lat, lbm_desc *out)
 lbm_status lbm_init_equilibrium(lbm_lattice *lat, const double *rho, const double *ux, const double *uy)
 {
     if (!lat || !rho || !ux || !uy) return fail(LBM_E_INVAL, "NULL argument");
+    if (lat->pool) return busy(lat);
     hipError_t e;
     const bool sixteen = lat->v.storage == LBM_STORE_F16 || lat->v.storage == LBM_STORE_BF16;
     if (lat->desc.scale_exp == LBM_SCALE_AUTO) {
@@ -315,6 +307,7 @@ lbm_status lbm_step(lbm_lattice *lat, int64_t n)
     if (!lat) return fail(LBM_E_INVAL, "lattice is NULL");
     if (n < 0) return fail(LBM_E_INVAL, "n must be >= 0");
     if (!lat->initialized) return fail(LBM_E_STATE, "lbm_step before lbm_init_equilibrium");
+    if (lat->pool) return busy(lat);
     for (int64_t k = 0; k < n; ++k) {
         hipError_t e = lbm::launch_step(lat->v, lat->buf[lat->cur], lat->buf[lat->cur ^ 1], lat->launch, lat->stream);
         if (e != hipSuccess) return hip_fail(e, "step launch");
@@ -328,6 +321,7 @@ lbm_status lbm_read_moments(lbm_lattice *lat, double *rho, double *ux, double *u
 {
     if (!lat || !rho || !ux || !uy) return fail(LBM_E_INVAL, "NULL argument");
     if (!lat->initialized) return fail(LBM_E_STATE, "read before init");
+    if (lat->pool) return busy(lat);
     hipError_t e = lbm::launch_moments(lat->v, lat->buf[lat->cur], rho, ux, uy, lat->stream);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "moments");
 }
@@ -336,6 +330,7 @@ lbm_status lbm_diagnostics(lbm_lattice *lat, double out[4])
 {
     if (!lat || !out) return fail(LBM_E_INVAL, "NULL argument");
     if (!lat->initialized) return fail(LBM_E_STATE, "diagnostics before init");
+    if (lat->pool) return busy(lat);
     hipError_t e = lbm::launch_diagnostics(lat->v, lat->buf[lat->cur], lat->partials, lat->result, lat->stream);
     if (e != hipSuccess) return hip_fail(e, "diagnostics");
     double h[4];
@@ -352,6 +347,7 @@ lbm_status lbm_project(lbm_lattice *lat, int32_t mx, int32_t my, double *dev_out
 {
     if (!lat || !dev_out) return fail(LBM_E_INVAL, "NULL argument");
     if (!lat->initialized) return fail(LBM_E_STATE, "project before init");
+    if (lat->pool) return busy(lat);
     hipError_t e = lbm::launch_project(lat->v, lat->buf[lat->cur], mx, my, lat->partials, dev_out, lat->stream);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "project");
 }
@@ -360,6 +356,7 @@ lbm_status lbm_read_populations(lbm_lattice *lat, double *dev_f)
 {
     if (!lat || !dev_f) return fail(LBM_E_INVAL, "NULL argument");
     if (!lat->initialized) return fail(LBM_E_STATE, "read before init");
+    if (lat->pool) return busy(lat);
     hipError_t e = lbm::launch_read_populations(lat->v, lat->buf[lat->cur], dev_f, lat->stream);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "read populations");
 }
@@ -367,6 +364,7 @@ lbm_status lbm_read_populations(lbm_lattice *lat, double *dev_f)
 lbm_status lbm_write_populations(lbm_lattice *lat, const double *dev_f)
 {
     if (!lat || !dev_f) return fail(LBM_E_INVAL, "NULL argument");
+    if (lat->pool) return busy(lat);
     if (!lat->initialized && lat->desc.scale_exp == LBM_SCALE_AUTO &&
         (lat->v.storage == LBM_STORE_F16 || lat->v.storage == LBM_STORE_BF16))
         return fail(LBM_E_STATE, "16-bit storage with automatic scale: init before writing populations");
@@ -382,6 +380,7 @@ lbm_status lbm_save_state(lbm_lattice *lat, void *dev_dst)
 {
     if (!lat || !dev_dst) return fail(LBM_E_INVAL, "NULL argument");
     if (!lat->initialized) return fail(LBM_E_STATE, "save before init");
+    if (lat->pool) return busy(lat);
     hipError_t e = hipMemcpyAsync(dev_dst, lat->buf[lat->cur], lat->state_bytes, hipMemcpyDeviceToDevice, lat->stream);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "hipMemcpyAsync");
 }
@@ -390,6 +389,7 @@ lbm_status lbm_load_state(lbm_lattice *lat, const void *dev_src, int64_t t)
 {
     if (!lat || !dev_src) return fail(LBM_E_INVAL, "NULL argument");
     if (t < 0) return fail(LBM_E_INVAL, "t must be >= 0");
+    if (lat->pool) return busy(lat);
     if (!lat->initialized && lat->desc.scale_exp == LBM_SCALE_AUTO &&
         (lat->v.storage == LBM_STORE_F16 || lat->v.storage == LBM_STORE_BF16))
         return fail(LBM_E_STATE, "16-bit storage with automatic scale: init before loading a state");
@@ -423,6 +423,7 @@ lbm_status lbm_time_launches(lbm_lattice *lat, int32_t n, double *avg_us)
 {
     if (!lat || !avg_us || n < 1) return fail(LBM_E_INVAL, "bad argument");
     if (!lat->initialized) return fail(LBM_E_STATE, "time before init");
+    if (lat->pool) return busy(lat);
     return time_shape(lat, lat->launch, n, avg_us);
 }
 
@@ -430,6 +431,7 @@ lbm_status lbm_tune(lbm_lattice *lat, int32_t reps, lbm_launch *best, double *be
 {
     if (!lat || reps < 1) return fail(LBM_E_INVAL, "bad argument");
     if (!lat->initialized) return fail(LBM_E_STATE, "tune before init");
+    if (lat->pool) return busy(lat);
     double best_t = INFINITY;
     lbm_launch best_c = lat->launch;
     auto sweep = [&](const std::vector<lbm_launch> &cands) -> lbm_status {

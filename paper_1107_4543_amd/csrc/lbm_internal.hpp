@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "../../include/lbm.h"
+#include "lbm_device.hpp"
 
 namespace lbm {
 
@@ -45,4 +46,67 @@ hipError_t launch_diagnostics(const View &v, const void *src, double *partials, 
 hipError_t launch_project(const View &v, const void *src, int32_t mx, int32_t my,
                           double *partials, double *out, hipStream_t st);
 
+// ---- batched stepping (pool) --------------------------------------------------
+
+// Storage/compute class of a lattice: storage * 2 + compute (8 values).
+constexpr int kClasses = 8;
+
+// Device-resident member record.  t_done advances on the device (commit
+// kernel) so that a recorded step loop stays valid while members come and go.
+struct PoolMember {
+    const void *buf[2];
+    int32_t nx, ny, pitch, cur0;   // cur0: buffer holding the state when added
+    int64_t plane;
+    int64_t t_done, t_target;      // steps done since added / steps requested
+    Relax<float> rf;
+    Relax<double> rd;
+    float scale, inv_scale;
+    int32_t cls, pad;
+};
+
+// A tile: nrows whole rows of one member, starting at row y0.
+struct PoolTile {
+    int32_t member, y0, nrows, pad;
+};
+
+struct PoolHeader {
+    int32_t begin[kClasses], end[kClasses];   // tile range of each class
+};
+
+// Sets the text returned by lbm_last_error() on the calling thread.
+void set_error_text(const char *msg);
+
+Relax<float> relax_f32(const View &v);
+Relax<double> relax_f64(const View &v);
+
+// One step (index k within the current chunk) of every active member of class cls.
+hipError_t launch_pool_step(int cls, const PoolHeader *hdr, const PoolMember *mem, const PoolTile *tiles, int k,
+                            int grid, int block, hipStream_t st);
+// t_done += min(kk, t_target - t_done) for members [0, nmem).
+hipError_t launch_pool_commit(PoolMember *mem, int nmem, int kk, hipStream_t st);
+// Kernel entry points and argument layout for graph nodes.
+void *pool_step_kernel(int cls);
+void *pool_commit_kernel();
+
 }  // namespace lbm
+
+struct lbm_pool;
+
+// Host handle of one lattice (defined here so that the pool can drive it).
+struct lbm_lattice {
+    lbm::View v;
+    lbm_desc desc;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    size_t buf_bytes = 0;      // bytes of one buffer (aligned)
+    size_t state_bytes = 0;    // bytes of one buffer's planes (exact)
+    void *buf[2] = {nullptr, nullptr};
+    int cur = 0;
+    double *partials = nullptr;
+    double *result = nullptr;
+    hipStream_t stream = nullptr;
+    int64_t t = 0;
+    bool initialized = false;
+    lbm_launch launch{};
+    lbm_pool *pool = nullptr;  // non-NULL while a pool advances this lattice
+};

@@ -89,6 +89,32 @@ __device__ __forceinline__ typename Store<S>::wide ld(const typename Store<S>::r
     else return Store<S>::widen(*p);
 }
 
+// The nine pulled values of cell (x, y): population i comes from x - v_i.
+// r0, rm, rp: offsets of rows y, y-1, y+1; xm, xp: columns x-1, x+1 (wrapped).
+template <typename S, bool NT>
+__device__ __forceinline__ void gather9(const typename Store<S>::raw *__restrict__ src, int64_t P, int64_t r0,
+                                        int64_t rm, int64_t rp, int x, int xm, int xp,
+                                        typename Store<S>::wide w[9])
+{
+    w[0] = ld<S, NT>(src + 0 * P + r0 + x);
+    w[1] = ld<S, NT>(src + 1 * P + r0 + xm);
+    w[2] = ld<S, NT>(src + 2 * P + rm + x);
+    w[3] = ld<S, NT>(src + 3 * P + r0 + xp);
+    w[4] = ld<S, NT>(src + 4 * P + rp + x);
+    w[5] = ld<S, NT>(src + 5 * P + rm + xm);
+    w[6] = ld<S, NT>(src + 6 * P + rm + xp);
+    w[7] = ld<S, NT>(src + 7 * P + rp + xp);
+    w[8] = ld<S, NT>(src + 8 * P + rp + xm);
+}
+
+template <typename S>
+__device__ __forceinline__ void store9(typename Store<S>::raw *__restrict__ dst, int64_t P, int64_t r0, int x,
+                                       const typename Store<S>::wide w[9])
+{
+#pragma unroll
+    for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(Store<S>::narrow(w[i]), dst + i * P + r0 + x);
+}
+
 // One cell per lane: nine direct (possibly misaligned) loads.
 // FLAGS bit 0: non-temporal loads; bit 1: the nine loads of the lane's next
 // row are issued before the current row is collided and stored.
@@ -112,16 +138,7 @@ __global__ void __launch_bounds__(1024) k_step_v1(StepArgs<C> a)
     auto gather = [&](int y, W w[9]) {
         const int ym = (y == 0 ? a.ny : y) - 1;
         const int yp = (y + 1 == a.ny) ? 0 : y + 1;
-        const int64_t r0 = (int64_t)y * a.pitch, rm = (int64_t)ym * a.pitch, rp = (int64_t)yp * a.pitch;
-        w[0] = ld<S, NT>(src + 0 * P + r0 + x);
-        w[1] = ld<S, NT>(src + 1 * P + r0 + xm);
-        w[2] = ld<S, NT>(src + 2 * P + rm + x);
-        w[3] = ld<S, NT>(src + 3 * P + r0 + xp);
-        w[4] = ld<S, NT>(src + 4 * P + rp + x);
-        w[5] = ld<S, NT>(src + 5 * P + rm + xm);
-        w[6] = ld<S, NT>(src + 6 * P + rm + xp);
-        w[7] = ld<S, NT>(src + 7 * P + rp + xp);
-        w[8] = ld<S, NT>(src + 8 * P + rp + xm);
+        gather9<S, NT>(src, P, (int64_t)y * a.pitch, (int64_t)ym * a.pitch, (int64_t)yp * a.pitch, x, xm, xp, w);
     };
     int y = tile_y * a.tile_h + threadIdx.y;
     if (y >= a.ny) return;
@@ -135,9 +152,7 @@ __global__ void __launch_bounds__(1024) k_step_v1(StepArgs<C> a)
             if (more) gather(yn, nxt);
         }
         cell_update<S, C>(w, a.r, a.scale, a.inv_scale);
-        const int64_t r0 = (int64_t)y * a.pitch;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(Store<S>::narrow(w[i]), dst + i * P + r0 + x);
+        store9<S>(dst, P, (int64_t)y * a.pitch, x, w);
         if (!more) return;
         if constexpr (PIPE) {
 #pragma unroll
@@ -146,6 +161,60 @@ __global__ void __launch_bounds__(1024) k_step_v1(StepArgs<C> a)
             gather(yn, w);
         }
         y = yn;
+    }
+}
+
+// Row strips: a workgroup owns whole rows and walks each one in chunks of
+// blockDim.x cells.  The cache line that two neighbouring chunks of an
+// x-shifted population share is then read twice by the same workgroup in
+// quick succession (an L2 hit) instead of by two workgroups that may sit on
+// different XCDs.  FLAGS as for k_step_v1 (bit 1 prefetches the next chunk).
+template <typename S, typename C, int FLAGS>
+__global__ void __launch_bounds__(1024) k_step_strip(StepArgs<C> a)
+{
+    using R = typename Store<S>::raw;
+    using W = typename Store<S>::wide;
+    constexpr bool NT = (FLAGS & 1) != 0;
+    constexpr bool PIPE = (FLAGS & 2) != 0;
+    int bid = blockIdx.x;
+    if (a.xcd_remap) bid = remap_xcd(bid, a.nblocks);
+    const R *__restrict__ src = (const R *)a.src;
+    R *__restrict__ dst = (R *)a.dst;
+    const int64_t P = a.plane;
+    const int y0 = bid * a.tile_h + threadIdx.y;
+    for (int rr = 0; rr < a.rows; ++rr) {
+        const int y = y0 + rr * blockDim.y;
+        if (y >= a.ny) return;
+        const int ym = (y == 0 ? a.ny : y) - 1;
+        const int yp = (y + 1 == a.ny) ? 0 : y + 1;
+        const int64_t r0 = (int64_t)y * a.pitch, rm = (int64_t)ym * a.pitch, rp = (int64_t)yp * a.pitch;
+        auto gather = [&](int x, W w[9]) {
+            const int xm = (x == 0 ? a.nx : x) - 1;
+            const int xp = (x + 1 == a.nx) ? 0 : x + 1;
+            gather9<S, NT>(src, P, r0, rm, rp, x, xm, xp, w);
+        };
+        int x = threadIdx.x;
+        if (x >= a.nx) continue;
+        W w[9];
+        gather(x, w);
+        while (true) {
+            const int xn = x + blockDim.x;
+            const bool more = xn < a.nx;
+            W nxt[9];
+            if constexpr (PIPE) {
+                if (more) gather(xn, nxt);
+            }
+            cell_update<S, C>(w, a.r, a.scale, a.inv_scale);
+            store9<S>(dst, P, r0, x, w);
+            if (!more) break;
+            if constexpr (PIPE) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) w[i] = nxt[i];
+            } else {
+                gather(xn, w);
+            }
+            x = xn;
+        }
     }
 }
 
@@ -235,6 +304,70 @@ __global__ void __launch_bounds__(1024) k_step_vec(StepArgs<C> a)
             }
         }
     }
+}
+
+// ---- batched step over a pool of lattices ----------------------------------------
+//
+// One launch advances every active member of one storage class by one step.
+// The grid is persistent (a fixed number of workgroups strides over the tile
+// table), so the same launch serves any membership.  A tile is nrows whole
+// rows of one member; its cells are walked as a flattened (row, x) index so
+// narrow lattices still fill whole waves.  Member k is active in launch k of
+// a chunk while t_done + k < t_target; its source buffer alternates with
+// t_done + k.  The per-cell work is the same gather9 / cell_update / store9
+// as the single-lattice kernels, so a lattice gives bit-identical results
+// alone or in a pool.
+
+template <typename C>
+__device__ __forceinline__ Relax<C> member_relax(const PoolMember *m);
+template <>
+__device__ __forceinline__ Relax<float> member_relax<float>(const PoolMember *m) { return m->rf; }
+template <>
+__device__ __forceinline__ Relax<double> member_relax<double>(const PoolMember *m) { return m->rd; }
+
+template <typename S, typename C>
+__global__ void __launch_bounds__(1024) k_pool_step(const PoolHeader *hdr, const PoolMember *mem,
+                                                     const PoolTile *tiles, int cls, int k)
+{
+    using R = typename Store<S>::raw;
+    using W = typename Store<S>::wide;
+    const int begin = hdr->begin[cls], end = hdr->end[cls];
+    for (int ti = begin + (int)blockIdx.x; ti < end; ti += (int)gridDim.x) {
+        const PoolTile tile = tiles[ti];
+        const PoolMember *m = mem + tile.member;
+        const int64_t done = m->t_done;
+        if (done + k >= m->t_target) continue;
+        const int par = (int)((m->cur0 + done + k) & 1);
+        const R *__restrict__ src = (const R *)m->buf[par];
+        R *__restrict__ dst = (R *)m->buf[par ^ 1];
+        const int nx = m->nx, ny = m->ny, pitch = m->pitch;
+        const int64_t P = m->plane;
+        const Relax<C> r = member_relax<C>(m);
+        const float scale = m->scale, inv_scale = m->inv_scale;
+        const int ncell = tile.nrows * nx;
+        for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
+            const int dy = c / nx;
+            const int x = c - dy * nx;
+            const int y = tile.y0 + dy;
+            const int xm = (x == 0 ? nx : x) - 1;
+            const int xp = (x + 1 == nx) ? 0 : x + 1;
+            const int ym = (y == 0 ? ny : y) - 1;
+            const int yp = (y + 1 == ny) ? 0 : y + 1;
+            const int64_t r0 = (int64_t)y * pitch;
+            W w[9];
+            gather9<S, false>(src, P, r0, (int64_t)ym * pitch, (int64_t)yp * pitch, x, xm, xp, w);
+            cell_update<S, C>(w, r, scale, inv_scale);
+            store9<S>(dst, P, r0, x, w);
+        }
+    }
+}
+
+__global__ void k_pool_commit(PoolMember *mem, int nmem, int kk)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nmem) return;
+    const int64_t rem = mem[i].t_target - mem[i].t_done;
+    if (rem > 0) mem[i].t_done += rem < kk ? rem : (int64_t)kk;
 }
 
 // ---- block reductions (fixed order, deterministic) ---------------------------
@@ -521,9 +654,9 @@ hipError_t launch_step_typed(const View &v, const void *src, void *dst, const lb
     a.nx = v.nx;
     a.ny = v.ny;
     a.pitch = v.pitch;
-    const int vx = 1 << cfg.variant;
+    const int vx = cfg.variant <= 3 ? 1 << cfg.variant : 1;
     const int tile_w = cfg.block_x * vx;
-    a.tiles_x = (v.nx + tile_w - 1) / tile_w;
+    a.tiles_x = cfg.variant == 4 ? 1 : (v.nx + tile_w - 1) / tile_w;
     a.tile_h = cfg.block_y * cfg.rows;
     a.rows = cfg.rows;
     const int tiles_y = (v.ny + a.tile_h - 1) / a.tile_h;
@@ -546,6 +679,10 @@ hipError_t launch_step_typed(const View &v, const void *src, void *dst, const lb
     case 9: hipLaunchKernelGGL((k_step_vec<S, C, 4, 1>), grid, block, 0, st, a); break;
     case 12: hipLaunchKernelGGL((k_step_vec<S, C, 8, 0>), grid, block, 0, st, a); break;
     case 13: hipLaunchKernelGGL((k_step_vec<S, C, 8, 1>), grid, block, 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_step_strip<S, C, 0>), grid, block, 0, st, a); break;
+    case 17: hipLaunchKernelGGL((k_step_strip<S, C, 1>), grid, block, 0, st, a); break;
+    case 18: hipLaunchKernelGGL((k_step_strip<S, C, 2>), grid, block, 0, st, a); break;
+    case 19: hipLaunchKernelGGL((k_step_strip<S, C, 3>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -644,14 +781,14 @@ size_t storage_bytes(int32_t storage)
 
 bool step_shape_supported(const View &v, const lbm_launch &cfg)
 {
-    if (cfg.variant < 0 || cfg.variant > 3) return false;
+    if (cfg.variant < 0 || cfg.variant > 4) return false;
     if (cfg.block_x < 1 || cfg.block_y < 1 || cfg.rows < 1 || cfg.rows > 64) return false;
     if (cfg.block_x * cfg.block_y > 1024 || cfg.block_x * cfg.block_y < 64) return false;
     if (cfg.block_x % 64 != 0 && cfg.block_x * cfg.block_y % 64 != 0) return false;
     if (cfg.xcd_remap != 0 && cfg.xcd_remap != 1) return false;
     if (cfg.flags < 0 || cfg.flags > 3) return false;
-    if ((cfg.flags & 2) && cfg.variant != 0) return false;     // row pipelining: one-cell kernel only
-    if (cfg.variant > 0) {
+    if ((cfg.flags & 2) && cfg.variant != 0 && cfg.variant != 4) return false;   // pipelining: one-cell kernels
+    if (cfg.variant >= 1 && cfg.variant <= 3) {
         const int vx = 1 << cfg.variant;
         if (cfg.block_x % 64 != 0 || v.nx % vx != 0) return false;
     }
@@ -703,6 +840,44 @@ hipError_t launch_project(const View &v, const void *src, int32_t mx, int32_t my
                           hipStream_t st)
 {
     return dispatch_storage<ProjectF>(v.storage, v, src, mx, my, partials, out, st);
+}
+
+Relax<float> relax_f32(const View &v) { return make_relax<float>(v); }
+Relax<double> relax_f64(const View &v) { return make_relax<double>(v); }
+
+void *pool_step_kernel(int cls)
+{
+    switch (cls) {
+    case LBM_STORE_F64 * 2 + LBM_COMPUTE_F64: return reinterpret_cast<void *>(&k_pool_step<double, double>);
+    case LBM_STORE_F64 * 2 + LBM_COMPUTE_F32: return reinterpret_cast<void *>(&k_pool_step<double, float>);
+    case LBM_STORE_F32 * 2 + LBM_COMPUTE_F32: return reinterpret_cast<void *>(&k_pool_step<float, float>);
+    case LBM_STORE_F16 * 2 + LBM_COMPUTE_F32: return reinterpret_cast<void *>(&k_pool_step<f16_tag, float>);
+    case LBM_STORE_BF16 * 2 + LBM_COMPUTE_F32: return reinterpret_cast<void *>(&k_pool_step<bf16_tag, float>);
+    default: return nullptr;
+    }
+}
+
+void *pool_commit_kernel() { return reinterpret_cast<void *>(&k_pool_commit); }
+
+hipError_t launch_pool_step(int cls, const PoolHeader *hdr, const PoolMember *mem, const PoolTile *tiles, int k,
+                            int grid, int block, hipStream_t st)
+{
+    const dim3 g(grid), b(block);
+    switch (cls) {
+    case LBM_STORE_F64 * 2 + LBM_COMPUTE_F64: hipLaunchKernelGGL((k_pool_step<double, double>), g, b, 0, st, hdr, mem, tiles, cls, k); break;
+    case LBM_STORE_F64 * 2 + LBM_COMPUTE_F32: hipLaunchKernelGGL((k_pool_step<double, float>), g, b, 0, st, hdr, mem, tiles, cls, k); break;
+    case LBM_STORE_F32 * 2 + LBM_COMPUTE_F32: hipLaunchKernelGGL((k_pool_step<float, float>), g, b, 0, st, hdr, mem, tiles, cls, k); break;
+    case LBM_STORE_F16 * 2 + LBM_COMPUTE_F32: hipLaunchKernelGGL((k_pool_step<f16_tag, float>), g, b, 0, st, hdr, mem, tiles, cls, k); break;
+    case LBM_STORE_BF16 * 2 + LBM_COMPUTE_F32: hipLaunchKernelGGL((k_pool_step<bf16_tag, float>), g, b, 0, st, hdr, mem, tiles, cls, k); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pool_commit(PoolMember *mem, int nmem, int kk, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pool_commit, dim3((nmem + 255) / 256), dim3(256), 0, st, mem, nmem, kk);
+    return hipGetLastError();
 }
 
 }  // namespace lbm

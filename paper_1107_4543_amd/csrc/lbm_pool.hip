@@ -1,0 +1,577 @@
+// Pool of lattices advanced together: batched stepping with a recorded step
+// loop (HIP graph), continuous membership, per-member step counts.
+//
+// Device side (carved from the caller's pool workspace):
+//   [ PoolHeader ][ PoolMember x max_members ][ PoolTile x max_tiles ]
+// Host side: a mirror of every member's progress.  Progress is deterministic
+// (a chunk of kk steps advances each member by min(kk, remaining)), so the
+// host always knows t_done without reading the device, and the device copy
+// of t_done is advanced by a commit kernel at the end of every chunk.  Tables
+// are rebuilt on the host and uploaded (stream-ordered) only when membership
+// changes; the recorded graphs read them through fixed device pointers and
+// stay valid.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "lbm_internal.hpp"
+
+namespace {
+
+lbm_status pfail(lbm_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    lbm::set_error_text(buf);
+    return s;
+}
+
+lbm_status phip(hipError_t e, const char *what) { return pfail(LBM_E_HIP, "%s: %s", what, hipGetErrorString(e)); }
+
+size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct Slot {
+    lbm_lattice *lat = nullptr;
+    int64_t t0 = 0, t_done = 0, t_target = 0;
+    int cur0 = 0;
+    bool finishing = false;          // reached t_target; waiting for poll
+    hipEvent_t ev_in = nullptr;      // lattice stream -> pool stream
+    hipEvent_t ev_done = nullptr;    // pool stream -> lattice stream
+};
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+int class_of(const lbm_lattice *L) { return L->v.storage * 2 + L->v.compute; }
+
+}  // namespace
+
+struct lbm_pool {
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    int max_members = 0, max_tiles = 0;
+    lbm::PoolHeader *d_hdr = nullptr;
+    lbm::PoolMember *d_mem = nullptr;
+    lbm::PoolTile *d_tiles = nullptr;
+    size_t table_bytes = 0;
+    void *stage = nullptr;           // pinned host staging of the tables
+    hipEvent_t ev_stage = nullptr;
+    bool stage_pending = false;
+    bool dirty = true;
+    unsigned class_mask = 0;         // classes with tiles in the uploaded tables
+    int ntiles = 0;
+    lbm_pool_shape shape{4096, 256, 2048, 32};
+    std::vector<Slot> slots;
+    std::vector<int> finishing;      // slot indices in completion order
+    std::map<unsigned, GraphEntry> graphs;
+};
+
+namespace {
+
+int tile_rows(const lbm_pool_shape &sh, const lbm_lattice *L)
+{
+    int r = sh.tile_cells / std::max(1, L->v.nx);
+    return std::max(1, std::min(r, L->v.ny));
+}
+
+int tiles_of(const lbm_pool_shape &sh, const lbm_lattice *L)
+{
+    const int r = tile_rows(sh, L);
+    return (L->v.ny + r - 1) / r;
+}
+
+void drop_graphs(lbm_pool *P)
+{
+    for (auto &kv : P->graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    P->graphs.clear();
+}
+
+// Rebuilds the member and tile tables on the host and uploads them.
+lbm_status upload(lbm_pool *P)
+{
+    if (!P->dirty) return LBM_OK;
+    hipError_t e;
+    if (P->stage_pending) {
+        if ((e = hipEventSynchronize(P->ev_stage)) != hipSuccess) return phip(e, "hipEventSynchronize");
+        P->stage_pending = false;
+    }
+    char *base = (char *)P->stage;
+    lbm::PoolHeader *hdr = (lbm::PoolHeader *)base;
+    lbm::PoolMember *mem = (lbm::PoolMember *)(base + ((char *)P->d_mem - P->ws));
+    lbm::PoolTile *tiles = (lbm::PoolTile *)(base + ((char *)P->d_tiles - P->ws));
+    memset(base, 0, (size_t)((char *)P->d_tiles - P->ws));
+    struct T { int cls; int64_t cells; lbm::PoolTile t; };
+    std::vector<T> all;
+    for (int i = 0; i < P->max_members; ++i) {
+        const Slot &s = P->slots[i];
+        lbm::PoolMember &m = mem[i];
+        if (!s.lat) {
+            m.cls = -1;
+            continue;
+        }
+        const lbm_lattice *L = s.lat;
+        m.buf[0] = L->buf[0];
+        m.buf[1] = L->buf[1];
+        m.nx = L->v.nx;
+        m.ny = L->v.ny;
+        m.pitch = L->v.pitch;
+        m.cur0 = s.cur0;
+        m.plane = L->v.plane;
+        m.t_done = s.t_done;
+        m.t_target = s.t_target;
+        m.rf = lbm::relax_f32(L->v);
+        m.rd = lbm::relax_f64(L->v);
+        m.scale = (float)L->v.scale;
+        m.inv_scale = (float)L->v.inv_scale;
+        m.cls = class_of(L);
+        if (s.t_done >= s.t_target) continue;        // finished: no tiles
+        const int r = tile_rows(P->shape, L);
+        for (int y0 = 0; y0 < L->v.ny; y0 += r) {
+            T t;
+            t.cls = m.cls;
+            t.t.member = i;
+            t.t.y0 = y0;
+            t.t.nrows = std::min(r, L->v.ny - y0);
+            t.t.pad = 0;
+            t.cells = (int64_t)t.t.nrows * L->v.nx;
+            all.push_back(t);
+        }
+    }
+    if ((int)all.size() > P->max_tiles) return pfail(LBM_E_NOMEM, "pool needs %zu tiles, has %d", all.size(), P->max_tiles);
+    // group by class, largest tiles first (balances the strided persistent grid)
+    std::stable_sort(all.begin(), all.end(), [](const T &a, const T &b) {
+        return a.cls != b.cls ? a.cls < b.cls : a.cells > b.cells;
+    });
+    unsigned mask = 0;
+    for (int c = 0; c < lbm::kClasses; ++c) hdr->begin[c] = hdr->end[c] = 0;
+    for (size_t j = 0; j < all.size(); ++j) {
+        tiles[j] = all[j].t;
+        const int c = all[j].cls;
+        if (!(mask & (1u << c))) hdr->begin[c] = (int)j;
+        hdr->end[c] = (int)j + 1;
+        mask |= 1u << c;
+    }
+    P->ntiles = (int)all.size();
+    const size_t used = (size_t)((char *)P->d_tiles - P->ws) + sizeof(lbm::PoolTile) * all.size();
+    if ((e = hipMemcpyAsync(P->ws, P->stage, used, hipMemcpyHostToDevice, P->stream)) != hipSuccess)
+        return phip(e, "hipMemcpyAsync (pool tables)");
+    if ((e = hipEventRecord(P->ev_stage, P->stream)) != hipSuccess) return phip(e, "hipEventRecord");
+    P->stage_pending = true;
+    P->class_mask = mask;
+    P->dirty = false;
+    return LBM_OK;
+}
+
+// Records the step loop of `steps` launches per class in `mask`, then commit.
+lbm_status get_graph(lbm_pool *P, unsigned mask, hipGraphExec_t *out)
+{
+    auto it = P->graphs.find(mask);
+    if (it != P->graphs.end()) {
+        *out = it->second.exec;
+        return LBM_OK;
+    }
+    GraphEntry g;
+    hipError_t e;
+    if ((e = hipGraphCreate(&g.graph, 0)) != hipSuccess) return phip(e, "hipGraphCreate");
+    std::vector<hipGraphNode_t> prev, cur;
+    const lbm::PoolHeader *hdr = P->d_hdr;
+    const lbm::PoolMember *mem = P->d_mem;
+    const lbm::PoolTile *tiles = P->d_tiles;
+    for (int k = 0; k < P->shape.graph_steps; ++k) {
+        cur.clear();
+        for (int c = 0; c < lbm::kClasses; ++c) {
+            if (!(mask & (1u << c))) continue;
+            int cls = c, kk = k;
+            void *args[] = {(void *)&hdr, (void *)&mem, (void *)&tiles, (void *)&cls, (void *)&kk};
+            hipKernelNodeParams np{};
+            np.func = lbm::pool_step_kernel(c);
+            np.gridDim = dim3(P->shape.grid);
+            np.blockDim = dim3(P->shape.block);
+            np.sharedMemBytes = 0;
+            np.kernelParams = args;
+            np.extra = nullptr;
+            hipGraphNode_t n;
+            if ((e = hipGraphAddKernelNode(&n, g.graph, prev.empty() ? nullptr : prev.data(), prev.size(), &np)) !=
+                hipSuccess) {
+                (void)hipGraphDestroy(g.graph);
+                return phip(e, "hipGraphAddKernelNode");
+            }
+            cur.push_back(n);
+        }
+        prev.swap(cur);
+    }
+    lbm::PoolMember *memw = P->d_mem;
+    int nmem = P->max_members, kk = P->shape.graph_steps;
+    void *cargs[] = {(void *)&memw, (void *)&nmem, (void *)&kk};
+    hipKernelNodeParams cp{};
+    cp.func = lbm::pool_commit_kernel();
+    cp.gridDim = dim3((nmem + 255) / 256);
+    cp.blockDim = dim3(256);
+    cp.kernelParams = cargs;
+    hipGraphNode_t cn;
+    if ((e = hipGraphAddKernelNode(&cn, g.graph, prev.empty() ? nullptr : prev.data(), prev.size(), &cp)) !=
+        hipSuccess) {
+        (void)hipGraphDestroy(g.graph);
+        return phip(e, "hipGraphAddKernelNode (commit)");
+    }
+    if ((e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0)) != hipSuccess) {
+        (void)hipGraphDestroy(g.graph);
+        return phip(e, "hipGraphInstantiate");
+    }
+    P->graphs[mask] = g;
+    *out = g.exec;
+    return LBM_OK;
+}
+
+// Advances every active member by min(kk, remaining); kk <= graph_steps.
+lbm_status run_chunk(lbm_pool *P, int kk)
+{
+    hipError_t e;
+    if (kk == P->shape.graph_steps) {
+        hipGraphExec_t ex;
+        lbm_status st = get_graph(P, P->class_mask, &ex);
+        if (st != LBM_OK) return st;
+        if ((e = hipGraphLaunch(ex, P->stream)) != hipSuccess) return phip(e, "hipGraphLaunch");
+    } else {
+        for (int k = 0; k < kk; ++k)
+            for (int c = 0; c < lbm::kClasses; ++c) {
+                if (!(P->class_mask & (1u << c))) continue;
+                if ((e = lbm::launch_pool_step(c, P->d_hdr, P->d_mem, P->d_tiles, k, P->shape.grid, P->shape.block,
+                                               P->stream)) != hipSuccess)
+                    return phip(e, "pool step launch");
+            }
+        if ((e = lbm::launch_pool_commit(P->d_mem, P->max_members, kk, P->stream)) != hipSuccess)
+            return phip(e, "pool commit launch");
+    }
+    for (int i = 0; i < P->max_members; ++i) {
+        Slot &s = P->slots[i];
+        if (!s.lat || s.finishing) continue;
+        const int64_t rem = s.t_target - s.t_done;
+        s.t_done += std::min<int64_t>(rem, kk);
+        if (s.t_done >= s.t_target) {
+            s.finishing = true;
+            if ((e = hipEventRecord(s.ev_done, P->stream)) != hipSuccess) return phip(e, "hipEventRecord");
+            P->finishing.push_back(i);
+        }
+    }
+    return LBM_OK;
+}
+
+bool valid_shape(const lbm_pool_shape &s)
+{
+    return s.tile_cells >= 64 && s.tile_cells <= (1 << 22) && s.block >= 64 && s.block <= 1024 && s.block % 64 == 0 &&
+           s.grid >= 1 && s.grid <= (1 << 20) && s.graph_steps >= 1 && s.graph_steps <= 1024;
+}
+
+// Hands a member back to its lattice: host state and stream order.
+lbm_status release(lbm_pool *P, int i)
+{
+    Slot &s = P->slots[i];
+    lbm_lattice *L = s.lat;
+    hipError_t e;
+    if (!s.finishing) {
+        if ((e = hipEventRecord(s.ev_done, P->stream)) != hipSuccess) return phip(e, "hipEventRecord");
+    }
+    if ((e = hipStreamWaitEvent(L->stream, s.ev_done, 0)) != hipSuccess) return phip(e, "hipStreamWaitEvent");
+    L->t = s.t0 + s.t_done;
+    L->cur = (int)((s.cur0 + s.t_done) & 1);
+    L->pool = nullptr;
+    s.lat = nullptr;
+    s.finishing = false;
+    s.t_done = s.t_target = 0;
+    P->dirty = true;
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_pool_workspace_bytes(int32_t max_members, int32_t max_tiles)
+{
+    if (max_members < 1 || max_members > (1 << 20) || max_tiles < 1 || max_tiles > (1 << 26)) return 0;
+    return a256(sizeof(lbm::PoolHeader)) + a256(sizeof(lbm::PoolMember) * (size_t)max_members) +
+           a256(sizeof(lbm::PoolTile) * (size_t)max_tiles);
+}
+
+lbm_status lbm_pool_create(void *dev_ws, size_t ws_bytes, void *stream, int32_t max_members, int32_t max_tiles,
+                           lbm_pool **out)
+{
+    if (!out) return pfail(LBM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    const size_t need = lbm_pool_workspace_bytes(max_members, max_tiles);
+    if (need == 0) return pfail(LBM_E_INVAL, "max_members in [1, 2^20] and max_tiles in [1, 2^26] required");
+    if (!dev_ws || ((uintptr_t)dev_ws & 255u)) return pfail(LBM_E_INVAL, "workspace must be non-NULL and 256-byte aligned");
+    if (ws_bytes < need) return pfail(LBM_E_NOMEM, "pool workspace has %zu bytes, needs %zu", ws_bytes, need);
+    lbm_pool *P = new (std::nothrow) lbm_pool();
+    if (!P) return pfail(LBM_E_NOMEM, "host allocation failed");
+    P->ws = (char *)dev_ws;
+    P->ws_bytes = ws_bytes;
+    P->stream = (hipStream_t)stream;
+    P->max_members = max_members;
+    P->max_tiles = max_tiles;
+    P->d_hdr = (lbm::PoolHeader *)P->ws;
+    P->d_mem = (lbm::PoolMember *)(P->ws + a256(sizeof(lbm::PoolHeader)));
+    P->d_tiles = (lbm::PoolTile *)((char *)P->d_mem + a256(sizeof(lbm::PoolMember) * (size_t)max_members));
+    P->table_bytes = need;
+    P->slots.resize(max_members);
+    hipError_t e;
+    lbm_status st = LBM_OK;
+    if ((e = hipHostMalloc(&P->stage, need, hipHostMallocDefault)) != hipSuccess) st = phip(e, "hipHostMalloc");
+    if (st == LBM_OK && (e = hipEventCreateWithFlags(&P->ev_stage, hipEventDisableTiming)) != hipSuccess)
+        st = phip(e, "hipEventCreate");
+    for (int i = 0; i < max_members && st == LBM_OK; ++i) {
+        if ((e = hipEventCreateWithFlags(&P->slots[i].ev_in, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&P->slots[i].ev_done, hipEventDisableTiming)) != hipSuccess)
+            st = phip(e, "hipEventCreate");
+    }
+    if (st != LBM_OK) {
+        lbm_pool_destroy(P);
+        return st;
+    }
+    *out = P;
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_destroy(lbm_pool *pool)
+{
+    if (!pool) return pfail(LBM_E_INVAL, "pool is NULL");
+    // hand back members still in the pool (their stream waits for the pool)
+    for (int i = 0; i < pool->max_members; ++i)
+        if (pool->slots[i].lat) (void)release(pool, i);
+    if (pool->stage_pending) (void)hipEventSynchronize(pool->ev_stage);
+    drop_graphs(pool);
+    for (Slot &s : pool->slots) {
+        if (s.ev_in) (void)hipEventDestroy(s.ev_in);
+        if (s.ev_done) (void)hipEventDestroy(s.ev_done);
+    }
+    if (pool->ev_stage) (void)hipEventDestroy(pool->ev_stage);
+    if (pool->stage) (void)hipHostFree(pool->stage);
+    delete pool;
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_add(lbm_pool *pool, lbm_lattice *lat, int64_t nsteps)
+{
+    if (!pool || !lat) return pfail(LBM_E_INVAL, "NULL argument");
+    if (nsteps < 0) return pfail(LBM_E_INVAL, "nsteps must be >= 0");
+    if (!lat->initialized) return pfail(LBM_E_STATE, "lattice must be initialised before joining a pool");
+    if (lat->pool) return pfail(LBM_E_STATE, "lattice is already in a pool");
+    int free_slot = -1, tiles = 0;
+    for (int i = 0; i < pool->max_members; ++i) {
+        const Slot &s = pool->slots[i];
+        if (!s.lat) {
+            if (free_slot < 0) free_slot = i;
+        } else if (s.t_done < s.t_target) {
+            tiles += tiles_of(pool->shape, s.lat);
+        }
+    }
+    if (free_slot < 0) return pfail(LBM_E_NOMEM, "pool is full (%d members)", pool->max_members);
+    if (tiles + tiles_of(pool->shape, lat) > pool->max_tiles)
+        return pfail(LBM_E_NOMEM, "pool tile table is full (%d tiles)", pool->max_tiles);
+    Slot &s = pool->slots[free_slot];
+    hipError_t e;
+    if ((e = hipEventRecord(s.ev_in, lat->stream)) != hipSuccess) return phip(e, "hipEventRecord");
+    if ((e = hipStreamWaitEvent(pool->stream, s.ev_in, 0)) != hipSuccess) return phip(e, "hipStreamWaitEvent");
+    s.lat = lat;
+    s.t0 = lat->t;
+    s.cur0 = lat->cur;
+    s.t_done = 0;
+    s.t_target = nsteps;
+    s.finishing = false;
+    lat->pool = pool;
+    pool->dirty = true;
+    if (nsteps == 0) {
+        s.finishing = true;
+        if ((e = hipEventRecord(s.ev_done, pool->stream)) != hipSuccess) return phip(e, "hipEventRecord");
+        pool->finishing.push_back(free_slot);
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_remove(lbm_pool *pool, lbm_lattice *lat)
+{
+    if (!pool || !lat) return pfail(LBM_E_INVAL, "NULL argument");
+    if (lat->pool != pool) return pfail(LBM_E_STATE, "lattice is not in this pool");
+    for (int i = 0; i < pool->max_members; ++i)
+        if (pool->slots[i].lat == lat) {
+            pool->finishing.erase(std::remove(pool->finishing.begin(), pool->finishing.end(), i),
+                                  pool->finishing.end());
+            return release(pool, i);
+        }
+    return pfail(LBM_E_STATE, "lattice not found in pool");
+}
+
+lbm_status lbm_pool_step(lbm_pool *pool, int64_t nsteps)
+{
+    if (!pool) return pfail(LBM_E_INVAL, "pool is NULL");
+    if (nsteps < 0) return pfail(LBM_E_INVAL, "nsteps must be >= 0");
+    while (nsteps > 0) {
+        int64_t max_rem = 0;
+        for (const Slot &s : pool->slots)
+            if (s.lat && !s.finishing) max_rem = std::max(max_rem, s.t_target - s.t_done);
+        if (max_rem == 0) break;
+        lbm_status st = upload(pool);
+        if (st != LBM_OK) return st;
+        const int kk = (int)std::min<int64_t>({nsteps, (int64_t)pool->shape.graph_steps, max_rem});
+        if ((st = run_chunk(pool, kk)) != LBM_OK) return st;
+        nsteps -= kk;
+        // finished members keep their (now idle) tiles until the next upload
+        for (const Slot &s : pool->slots)
+            if (s.lat && s.finishing && s.t_done == s.t_target) {
+                pool->dirty = true;
+                break;
+            }
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_poll(lbm_pool *pool, lbm_lattice **done, int32_t cap, int32_t wait, int32_t *ndone)
+{
+    if (!pool || !ndone || cap < 0 || (cap > 0 && !done)) return pfail(LBM_E_INVAL, "bad argument");
+    *ndone = 0;
+    hipError_t e;
+    if (wait && !pool->finishing.empty() && cap > 0) {
+        if ((e = hipEventSynchronize(pool->slots[pool->finishing.front()].ev_done)) != hipSuccess)
+            return phip(e, "hipEventSynchronize");
+    }
+    std::vector<int> keep;
+    for (int i : pool->finishing) {
+        if (*ndone >= cap) {
+            keep.push_back(i);
+            continue;
+        }
+        e = hipEventQuery(pool->slots[i].ev_done);
+        if (e == hipErrorNotReady) {
+            keep.push_back(i);
+            continue;
+        }
+        if (e != hipSuccess) return phip(e, "hipEventQuery");
+        lbm_lattice *L = pool->slots[i].lat;
+        lbm_status st = release(pool, i);
+        if (st != LBM_OK) return st;
+        done[(*ndone)++] = L;
+    }
+    pool->finishing.swap(keep);
+    return LBM_OK;
+}
+
+int32_t lbm_pool_members(const lbm_pool *pool)
+{
+    if (!pool) return -1;
+    int n = 0;
+    for (const Slot &s : pool->slots) n += s.lat != nullptr;
+    return n;
+}
+
+int64_t lbm_pool_remaining(const lbm_pool *pool, const lbm_lattice *lat)
+{
+    if (!pool || !lat) return -1;
+    for (const Slot &s : pool->slots)
+        if (s.lat == lat) return s.t_target - s.t_done;
+    return -1;
+}
+
+lbm_status lbm_pool_get_shape(const lbm_pool *pool, lbm_pool_shape *out)
+{
+    if (!pool || !out) return pfail(LBM_E_INVAL, "NULL argument");
+    *out = pool->shape;
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_set_shape(lbm_pool *pool, const lbm_pool_shape *shape)
+{
+    if (!pool || !shape) return pfail(LBM_E_INVAL, "NULL argument");
+    if (!valid_shape(*shape)) return pfail(LBM_E_INVAL, "invalid pool shape");
+    int tiles = 0;
+    for (const Slot &s : pool->slots)
+        if (s.lat && s.t_done < s.t_target) tiles += tiles_of(*shape, s.lat);
+    if (tiles > pool->max_tiles) return pfail(LBM_E_NOMEM, "shape needs %d tiles, pool has %d", tiles, pool->max_tiles);
+    drop_graphs(pool);
+    pool->shape = *shape;
+    pool->dirty = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_time_launches(lbm_pool *pool, int32_t reps, double *avg_us)
+{
+    if (!pool || reps < 1 || !avg_us) return pfail(LBM_E_INVAL, "bad argument");
+    lbm_status st = upload(pool);
+    if (st != LBM_OK) return st;
+    hipEvent_t e0, e1;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return phip(e, "hipEventCreate");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return phip(e, "hipEventCreate");
+    }
+    // k = 0 without commit: every active member recomputes its next state
+    // into its other buffer; the state itself does not change.
+    auto launch_all = [&]() -> hipError_t {
+        for (int c = 0; c < lbm::kClasses; ++c) {
+            if (!(pool->class_mask & (1u << c))) continue;
+            hipError_t r = lbm::launch_pool_step(c, pool->d_hdr, pool->d_mem, pool->d_tiles, 0, pool->shape.grid,
+                                                 pool->shape.block, pool->stream);
+            if (r != hipSuccess) return r;
+        }
+        return hipSuccess;
+    };
+    e = launch_all();
+    if (e == hipSuccess) e = hipEventRecord(e0, pool->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_all();
+    if (e == hipSuccess) e = hipEventRecord(e1, pool->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return phip(e, "pool timing");
+    *avg_us = 1000.0 * ms / reps;
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_tune(lbm_pool *pool, int32_t reps, lbm_pool_shape *best, double *best_us)
+{
+    if (!pool || reps < 1) return pfail(LBM_E_INVAL, "bad argument");
+    const lbm_pool_shape keep = pool->shape;
+    lbm_pool_shape best_s = keep;
+    double best_t = INFINITY;
+    for (int cells : {1024, 2048, 4096, 8192, 16384})
+        for (int block : {256, 512, 1024})
+            for (int grid : {1024, 2048, 4096}) {
+                lbm_pool_shape s = keep;
+                s.tile_cells = cells;
+                s.block = block;
+                s.grid = grid;
+                if (lbm_pool_set_shape(pool, &s) != LBM_OK) continue;
+                double us;
+                lbm_status st = lbm_pool_time_launches(pool, reps, &us);
+                if (st != LBM_OK) return st;
+                if (us < best_t) {
+                    best_t = us;
+                    best_s = s;
+                }
+            }
+    lbm_status st = lbm_pool_set_shape(pool, &best_s);
+    if (st != LBM_OK) return st;
+    if (best) *best = best_s;
+    if (best_us) *best_us = best_t;
+    return LBM_OK;
+}
+
+}  // extern "C"

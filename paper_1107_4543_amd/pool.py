@@ -1,0 +1,73 @@
+"""``Pool``: many lattices advanced together by the library's batched kernels
+(one persistent launch per storage class and step, the step loop replayed as
+a HIP graph).  Marshalling only; see include/lbm.h for the semantics."""
+import torch
+
+from . import _lib
+
+
+class Pool:
+    def __init__(self, max_members=256, max_tiles=1 << 16, device="cuda", stream=None):
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = _lib.lbm_pool_workspace_bytes(max_members, max_tiles)
+        if nbytes == 0:
+            raise _lib.LbmError(_lib.LBM_E_INVAL, "lbm_pool_workspace_bytes", "size out of range")
+        self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._h = _lib.lbm_pool_create(self._ws.data_ptr(), nbytes, self.stream.cuda_stream,
+                                       max_members, max_tiles)
+        self.max_members = max_members
+        self._members = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lbm_pool_destroy(self._h)
+            self._h = None
+            self._members.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, lat, nsteps):
+        _lib.lbm_pool_add(self._h, lat.handle, nsteps)
+        self._members[lat.handle.value] = lat
+        return self
+
+    def remove(self, lat):
+        _lib.lbm_pool_remove(self._h, lat.handle)
+        self._members.pop(lat.handle.value, None)
+        return self
+
+    def step(self, nsteps):
+        _lib.lbm_pool_step(self._h, nsteps)
+        return self
+
+    def poll(self, wait=False, cap=None):
+        """Finished lattices (they leave the pool)."""
+        hs = _lib.lbm_pool_poll(self._h, cap or self.max_members, wait)
+        return [self._members.pop(h) for h in hs]
+
+    @property
+    def members(self):
+        return _lib.lbm_pool_members(self._h)
+
+    def remaining(self, lat):
+        return _lib.lbm_pool_remaining(self._h, lat.handle)
+
+    @property
+    def shape(self):
+        return _lib.lbm_pool_get_shape(self._h).as_dict()
+
+    def set_shape(self, tile_cells=4096, block=256, grid=2048, graph_steps=32):
+        _lib.lbm_pool_set_shape(self._h, _lib.lbm_pool_shape(tile_cells, block, grid, graph_steps))
+        return self
+
+    def time_launches(self, reps=5):
+        return _lib.lbm_pool_time_launches(self._h, reps)
+
+    def tune(self, reps=5):
+        s, us = _lib.lbm_pool_tune(self._h, reps)
+        return s.as_dict(), us

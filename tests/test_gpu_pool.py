@@ -1,0 +1,166 @@
+"""Batched stepping (pools) on the GPU: every member advances exactly its own
+number of steps and ends bit-identical to the same lattice stepped alone;
+membership changes between steps; parity with the oracle; error paths."""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs
+import oracle
+from oracle import linear
+
+pytestmark = pytest.mark.gpu
+
+
+def make(nx, ny, s, storage="f32", seed=0, u0=(0.0, 0.0), amp=1e-3):
+    from paper_1107_4543_amd import Lattice
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + amp * rng.standard_normal((ny, nx))
+    ux = u0[0] + amp * rng.standard_normal((ny, nx))
+    uy = u0[1] + amp * rng.standard_normal((ny, nx))
+    lat = Lattice(nx, ny, *s, storage=storage, u0=u0, device="cuda:0")
+    lat.init(rho, ux, uy)
+    return lat, (rho, ux, uy)
+
+
+def twin(lat, fields, s):
+    from paper_1107_4543_amd import Lattice
+    t = Lattice(lat.nx, lat.ny, *s, storage=lat.storage, u0=(lat.desc.u0x, lat.desc.u0y), device="cuda:0",
+                scale_exp=lat.scale_exp)
+    return t.init(*fields)
+
+
+SETS = [[1.64, 1.54, 1.9, 1.98], [1.3, 1.1, 1.7, 1.85], [1.99, 1.962820428, 1.992761413, 1.999960001],
+        [1.2, 1.5, 1.4, 1.6], [1.5, 1.5, 1.5, 1.5], [1.8, 1.2, 1.95, 1.7]]
+SIZES = [(64, 64), (100, 37), (257, 64), (33, 190), (1, 9), (128, 128)]
+STORES = ["f32", "f16", "f64", "bf16", "f32", "f32"]
+STEPS = [37, 100, 0, 64, 5, 91]
+
+
+def test_members_match_alone_bitwise_with_own_step_counts():
+    from paper_1107_4543_amd.pool import Pool
+    pool = Pool(max_members=16, max_tiles=4096)
+    pool.set_shape(tile_cells=512, block=256, grid=64, graph_steps=16)
+    lats, twins = [], []
+    for i, ((nx, ny), s, st, n) in enumerate(zip(SIZES, SETS, STORES, STEPS)):
+        lat, f = make(nx, ny, s, st, seed=i, u0=(0.02 * (i % 2), 0.0))
+        lat.step(3)                                  # members need not start at t = 0
+        pool.add(lat, n)
+        lats.append(lat)
+        twins.append(twin(lat, f, s).step(3 + n))
+    pool.step(60)
+    torch.cuda.synchronize()
+    done = {id(l) for l in pool.poll()}
+    for lat, n in zip(lats, STEPS):
+        assert (id(lat) in done) == (n <= 60)
+    pool.step(1000)
+    torch.cuda.synchronize()
+    rest = pool.poll(wait=True)
+    while pool.members:
+        rest += pool.poll(wait=True)
+    for lat, tw, n in zip(lats, twins, STEPS):
+        assert lat.t == 3 + n
+        assert torch.equal(lat.populations(), tw.populations()), (lat.nx, lat.ny, lat.storage)
+    pool.close()
+
+
+def test_continuous_membership_and_remove():
+    from paper_1107_4543_amd import _lib
+    from paper_1107_4543_amd.pool import Pool
+    pool = Pool(max_members=4, max_tiles=1024)
+    pool.set_shape(tile_cells=1024, block=128, grid=32, graph_steps=8)
+    s = SETS[0]
+    a, fa = make(96, 40, s, "f32", seed=1)
+    b, fb = make(50, 70, s, "f32", seed=2)
+    c, fc = make(70, 20, s, "f64", seed=3)
+    pool.add(a, 50)
+    pool.step(20)                                     # 2 graph replays + 4 direct steps
+    pool.add(b, 30)                                   # joins while a is in flight
+    with pytest.raises(_lib.LbmError) as e:
+        a.step(1)
+    assert e.value.status == _lib.LBM_E_STATE
+    with pytest.raises(_lib.LbmError):
+        pool.add(a, 1)
+    pool.step(13)
+    pool.add(c, 40)
+    pool.step(11)
+    pool.remove(c)                                    # leaves after 11 of 40 steps
+    assert c.t == 11
+    assert pool.remaining(a) == 50 - 44 and pool.remaining(b) == 30 - 24
+    pool.step(100)
+    out = []
+    while pool.members:
+        out += pool.poll(wait=True)
+    assert {id(x) for x in out} == {id(a), id(b)}
+    assert a.t == 50 and b.t == 30
+    for lat, f, n in [(a, fa, 50), (b, fb, 30), (c, fc, 11)]:
+        assert torch.equal(lat.populations(), twin(lat, f, s).step(n).populations())
+    c.step(2)                                         # usable again after leaving
+    assert c.t == 13
+    pool.close()
+
+
+def test_pool_member_parity_with_oracle_fp64():
+    from paper_1107_4543_amd.pool import Pool
+    pool = Pool(max_members=4, max_tiles=512)
+    pool.set_shape(tile_cells=256, block=64, grid=16, graph_steps=10)
+    s = [1.64, 1.54, 1.9, float(linear.s_from_nu(1e-3))]
+    lat, (rho, ux, uy) = make(48, 30, s, "f64", seed=7, u0=(0.03, 0.0))
+    pool.add(lat, 77)
+    pool.step(77)
+    assert pool.poll(wait=True) == [lat]
+    ref = oracle.run(oracle.init(rho, ux, uy), s, 77)
+    f = lat.populations().cpu().numpy()
+    assert np.max(np.abs(f - ref)) <= 1e-12 * np.max(np.abs(ref))
+    pool.close()
+
+
+def test_pool_tune_and_timing_leave_states_unchanged():
+    from paper_1107_4543_amd.pool import Pool
+    pool = Pool(max_members=8, max_tiles=8192)
+    lats = []
+    for i in range(3):
+        lat, _ = make(128 + 32 * i, 96, SETS[i], "f32", seed=10 + i)
+        pool.add(lat, 10)
+        lats.append(lat)
+    shape, us = pool.tune(reps=2)
+    assert us > 0 and shape["tile_cells"] >= 1024
+    pool.time_launches(2)
+    for lat in lats:
+        pool.remove(lat)
+        assert lat.t == 0
+    # states untouched: stepping now equals stepping fresh twins
+    for i, lat in enumerate(lats):
+        _, f = make(128 + 32 * i, 96, SETS[i], "f32", seed=10 + i)
+        assert torch.equal(lat.step(4).populations(), twin(lat, f, SETS[i]).step(4).populations())
+    pool.close()
+
+
+def test_full_batch_of_256_lattices_matches_alone_on_a_sample():
+    # The batched workload: 256 lattices of log-uniform sides in [64, 1024],
+    # sampled rates (kept only if linearly stable), one pulse each, 500 steps.
+    from paper_1107_4543_amd import Lattice
+    from paper_1107_4543_amd import stability
+    from paper_1107_4543_amd.pool import Pool
+    w = lbm_inputs.WORKLOADS["batch256"]
+    specs = lbm_inputs.batch_specs(w["seed"], w["count"], steps=w["steps"], accept=stability.stable)
+    pool = Pool(max_members=256, max_tiles=1 << 16)
+    lats = []
+    for sp in specs:
+        lat = Lattice(sp.nx, sp.ny, *stability.rates(sp.relax), storage="f32", device="cuda:0")
+        lat.init(*sp.fields())
+        pool.add(lat, sp.steps)
+        lats.append(lat)
+    pool.step(w["steps"])
+    got = []
+    while pool.members:
+        got += pool.poll(wait=True)
+    assert len(got) == 256
+    for j in range(0, 256, 37):
+        sp = specs[j]
+        alone = Lattice(sp.nx, sp.ny, *stability.rates(sp.relax), storage="f32", device="cuda:0")
+        alone.init(*sp.fields()).step(sp.steps)
+        assert torch.equal(lats[j].populations(), alone.populations()), j
+        st, d = lats[j].diagnostics()
+        assert st == 0
+    pool.close()
