@@ -124,6 +124,123 @@ def copy_probe(nbytes, reps):
             "GBps": round(2 * nbytes / (us * 1e-6) / 1e9, 1)}
 
 
+def bench_batch256(args):
+    """256 independent lattices (sides log-uniform in [64, 1024], sampled
+    stable rates, one pulse each, FP32, 500 steps): the whole job in one pool
+    (persistent launches, recorded step loop, tuned tiles) against the same
+    256 lattices run one after another with one plain launch per step.  The
+    two give bit-identical fields (checked)."""
+    import torch
+
+    import lbm_inputs
+    from paper_1107_4543_amd import Lattice, stability
+    from paper_1107_4543_amd.pool import Pool
+    w = lbm_inputs.WORKLOADS["batch256"]
+    steps = w["steps"] if args.steps == 2000 else args.steps
+    draws = [0]
+
+    def accept(relax):
+        draws[0] += 1
+        return stability.stable(relax)
+
+    specs = lbm_inputs.batch_specs(w["seed"], w["count"], steps=steps, accept=accept)
+    dev = "cuda:0"
+    lats = [Lattice(sp.nx, sp.ny, *stability.rates(sp.relax), storage="f32", device=dev) for sp in specs]
+    fields = [sp.fields_torch(dev) for sp in specs]
+    cells = sum(sp.nx * sp.ny for sp in specs)
+
+    def init_all():
+        for lat, f in zip(lats, fields):
+            lat.init(*f)
+
+    pool = Pool(max_members=len(specs), max_tiles=1 << 17, device=dev)
+    init_all()
+    for lat in lats:
+        pool.add(lat, steps)
+    shape, _ = pool.tune(reps=3)
+    pool.step(steps)                                  # untimed warm-up pass (records the graph)
+    while pool.members:
+        pool.poll(wait=True)
+    init_all()
+    for lat in lats:
+        pool.add(lat, steps)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(pool.stream)
+    pool.step(steps)
+    e1.record(pool.stream)
+    torch.cuda.synchronize()
+    ms_batched = e0.elapsed_time(e1)
+    while pool.members:
+        pool.poll(wait=True)
+    batched_rho = [lat.moments()[0] for lat in lats]
+
+    init_all()
+    torch.cuda.synchronize()
+    e0.record()
+    for lat in lats:
+        lat.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_seq = e0.elapsed_time(e1)
+    equal = all(torch.equal(r, lat.moments()[0]) for r, lat in zip(batched_rho, lats))
+    pool.close()
+
+    lups = cells * steps
+    alg = 72 * lups
+    return {
+        "metric": METRIC, "value": round(lups / (ms_batched / 1e3) / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": steps, "warmup": steps, "ms_per_step": round(ms_batched / steps, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch256", "lattices": len(specs), "cells": cells, "steps": steps,
+                   "seed": w["seed"], "pool_shape": shape, "stability_draws": draws[0],
+                   "stability_acceptance": round(len(specs) / draws[0], 4)},
+        "roofline": {"bound": "hbm", "achieved": round(alg / (ms_batched / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(alg / (ms_batched / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "kernel": "k_pool_step (persistent, per storage class)",
+                     "algorithmic_bytes_per_launch": 72 * cells,
+                     "avg_launch_us": round(1e3 * ms_batched / steps, 3)},
+        "sequential_plain": {"value": round(lups / (ms_seq / 1e3) / 1e6, 1), "unit": "MLUPS",
+                             "ms": round(ms_seq, 2), "launches": len(specs) * steps,
+                             "launch_shape": lats[0].launch},
+        "speedup_vs_sequential": round(ms_seq / ms_batched, 3),
+        "bitwise_equal_to_sequential": bool(equal),
+    }
+
+
+def bench_serve(args):
+    """Poisson arrivals of simulation jobs (square side log-uniform in
+    [128, 4096], steps uniform in [200, 5000], FP32 or FP16 storage 50/50,
+    sampled stable rates, pulse or plane-wave initial fields), served with
+    continuous batching under an HBM budget and, on the same trace, one job
+    at a time with plain launches.  Latency = arrival to result on the host."""
+    import lbm_inputs
+    from paper_1107_4543_amd import stability
+    from paper_1107_4543_amd.serve import Server, run_plain, summarize
+    out = []
+    budget = int(args.budget_gb * 1e9)
+    for i, rate in enumerate(float(r) for r in args.rates.split(",")):
+        trace = lbm_inputs.serving_trace(100 + i, rate, args.jobs, accept=stability.stable)
+        srv = Server(budget, max_members=256)
+        served = srv.run(trace)
+        srv.close()
+        plain = run_plain(trace)
+        pd = {r.tag: r.diag for r in plain}
+        equal = all(r.diag == pd[r.tag] for r in served)
+        row = {"rate_jobs_per_s": rate, "jobs": len(trace), "served": summarize(served),
+               "plain": summarize(plain), "equal_results": bool(equal), "rejected": len(srv.rejected),
+               "peak_members": srv.peak_members, "peak_budget_gb": round(srv.peak_used / 1e9, 2)}
+        out.append(row)
+        print(json.dumps({"progress": row}), file=sys.stderr, flush=True)
+    top = out[-1]["served"]
+    return {"metric": METRIC, "value": top["aggregate_mlups"], "unit": "MLUPS", "n_gpus": 1,
+            "steps": None, "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32/f16", "data": "synthetic",
+            "config": {"workload": "serve", "jobs_per_rate": args.jobs, "budget_gb": args.budget_gb,
+                       "rates": args.rates},
+            "serving": out}
+
+
 def parse_launch(text):
     keys = ["variant", "block_x", "block_y", "rows", "xcd_remap", "flags"]
     vals = [int(v) for v in text.split(",")]
@@ -138,6 +255,12 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16", "bf16"])
+    ap.add_argument("--workload", default="waves4096", choices=["waves4096", "batch256", "serve"],
+                    help="waves4096: one 4096^2 lattice (default); batch256: 256 lattices, pool vs "
+                         "sequential; serve: Poisson job traces, continuous batching vs plain FIFO")
+    ap.add_argument("--rates", default="10,30,100,300,1000", help="serve: arrival rates (jobs/s)")
+    ap.add_argument("--jobs", type=int, default=40, help="serve: jobs per rate")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget for admitted jobs")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--launch", default=None,
                     help="fixed launch shape variant,block_x,block_y,rows,xcd_remap,flags (no tuning)")
@@ -158,6 +281,12 @@ def main():
 
     if args.probe == "copy":
         print(json.dumps({"probe": "copy", **copy_probe(args.probe_bytes, args.steps)}), flush=True)
+        return
+    if args.workload == "batch256":
+        print(json.dumps(bench_batch256(args)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps(bench_serve(args)), flush=True)
         return
 
     lat, cfg, rates, fields1, w = build_waves4096(args.storage)

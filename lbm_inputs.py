@@ -179,6 +179,27 @@ class LatticeSpec:
             return plane_waves(self.nx, self.ny, self.wave_mode, self.wave_amplitude, 0.0, 0.0)
         return pulses_field(self.nx, self.ny, [self.pulse])
 
+    def fields_torch(self, device):
+        """The same fields generated on a torch device (float64)."""
+        import torch
+        x = torch.arange(self.nx, dtype=torch.float64, device=device)[None, :]
+        y = torch.arange(self.ny, dtype=torch.float64, device=device)[:, None]
+        if self.init == "wave":
+            k = 2.0 * math.pi * self.wave_mode / self.nx
+            c = torch.cos(k * x).expand(self.ny, self.nx)
+            rho = 1.0 + self.wave_amplitude * c
+            ux = self.wave_amplitude * CS * c
+            uy = torch.zeros_like(rho)
+            return rho.contiguous(), ux.contiguous(), uy
+        p = self.pulse
+        dx = x - p.cx
+        dx = dx - self.nx * torch.round(dx / self.nx)
+        dy = y - p.cy
+        dy = dy - self.ny * torch.round(dy / self.ny)
+        rho = 1.0 + p.amplitude * torch.exp(-math.log(2.0) * (dx * dx + dy * dy) / (p.half_width ** 2))
+        z = torch.zeros_like(rho)
+        return rho.contiguous(), z, z.clone()
+
 
 def _log_uniform_int(rng, lo, hi):
     return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))

@@ -72,6 +72,9 @@ class Lattice:
         for a in self._fields:
             if tuple(a.shape) != (self.ny, self.nx):
                 raise ValueError(f"field shape {tuple(a.shape)} != {(self.ny, self.nx)}")
+            if self.stream != torch.cuda.current_stream(self.device):
+                self.stream.wait_stream(torch.cuda.current_stream(self.device))
+                a.record_stream(self.stream)
         with torch.cuda.stream(self.stream):
             _lib.lbm_init_equilibrium(self._h, *(a.data_ptr() for a in self._fields))
         return self

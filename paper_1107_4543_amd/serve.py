@@ -1,0 +1,195 @@
+"""Serving D2Q9 MRT simulation jobs on one GPU with continuous batching.
+
+A job is a lattice (size, relaxation rates, storage type, initial fields) and
+a number of steps.  ``Server.run`` replays a trace of jobs in real time:
+
+* jobs whose arrival time has passed wait in a FIFO queue;
+* the head of the queue is admitted as soon as its device footprint fits in
+  the HBM budget and the pool has a free member slot: its workspace is
+  allocated, its fields are generated on the device and it joins the pool
+  (its state stays on the device for its whole life);
+* the pool advances all admitted jobs together, one chunk of steps at a time
+  (persistent batched launches, recorded step loop), with at most two chunks
+  in flight so that admissions and completions are handled between chunks;
+* a job leaves the pool after exactly its own number of steps; its result
+  (FP64 mass/momentum diagnostics on the host, density/velocity fields on the
+  device) is read and its memory returned to the budget.
+
+``run_plain`` serves the same trace one job at a time in arrival order with
+one plain launch per step, for comparison.  Both paths use the same per-cell
+arithmetic, so every job's result is bit-identical in the two.
+"""
+import collections
+import math
+import time
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import torch
+
+from . import _lib
+from .lattice import Lattice
+from .pool import Pool
+from . import stability
+
+STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+HBM_GBPS_ESTIMATE = 6000.0      # for sizing chunks only
+
+
+@dataclass
+class JobResult:
+    tag: int
+    arrival: float
+    admitted: float
+    done: float
+    nx: int
+    ny: int
+    steps: int
+    storage: str
+    diag: List[float] = field(default_factory=list)
+    status: int = 0
+
+    @property
+    def latency(self):
+        return self.done - self.arrival
+
+
+def footprint(spec):
+    """Device bytes a job holds while admitted: its workspace plus its three
+    FP64 initial fields."""
+    d = _lib.lbm_desc()
+    d.nx, d.ny = spec.nx, spec.ny
+    d.storage = _lib.STORAGE[spec.storage]
+    d.compute = _lib.LBM_COMPUTE_F64 if spec.storage == "f64" else _lib.LBM_COMPUTE_F32
+    d.s_e, d.s_eps, d.s_q, d.s_nu = stability.rates(spec.relax)
+    d.rho0, d.u0x, d.u0y = 1.0, 0.0, 0.0
+    d.scale_exp = _lib.LBM_SCALE_AUTO
+    d.flags = 0
+    return _lib.lbm_workspace_bytes(d) + 24 * spec.nx * spec.ny
+
+
+def _new_lattice(spec, device, stream=None):
+    """Allocates, generates the initial fields and initialises on `stream`."""
+    stream = stream if stream is not None else torch.cuda.current_stream(device)
+    with torch.cuda.stream(stream):
+        lat = Lattice(spec.nx, spec.ny, *stability.rates(spec.relax), storage=spec.storage, device=device,
+                      stream=stream)
+        lat.init(*spec.fields_torch(device))
+    return lat
+
+
+def percentile(xs, q):
+    if not xs:
+        return float("nan")
+    s = sorted(xs)
+    k = (len(s) - 1) * q / 100.0
+    lo, hi = math.floor(k), math.ceil(k)
+    return s[lo] + (s[hi] - s[lo]) * (k - lo)
+
+
+class Server:
+    def __init__(self, hbm_budget_bytes, max_members=256, max_tiles=1 << 18, chunk_ms=10.0,
+                 device="cuda:0", screen=False, tune=False):
+        self.device = torch.device(device)
+        self.budget = int(hbm_budget_bytes)
+        self.pool = Pool(max_members=max_members, max_tiles=max_tiles, device=self.device)
+        self.max_members = max_members
+        self.chunk_ms = chunk_ms
+        self.screen = screen
+        self.tune = tune
+        self.used = 0
+        self.peak_used = 0
+        self.peak_members = 0
+        self.rejected = []
+        # Jobs are initialised and read back on a side stream: a finished
+        # job's readback then waits for its own last chunk only, not for the
+        # chunks enqueued after it on the pool's stream.
+        self.side = torch.cuda.Stream(self.device)
+
+    def _chunk_steps(self, active_bytes_per_step):
+        est_ms = active_bytes_per_step / (HBM_GBPS_ESTIMATE * 1e6)
+        return max(1, min(self.pool.shape["graph_steps"], int(self.chunk_ms / max(est_ms, 1e-6))))
+
+    def run(self, trace) -> List[JobResult]:
+        pending = collections.deque(sorted(trace, key=lambda s: s.arrival))
+        queue = collections.deque()
+        active = {}                                  # id(lattice) -> (spec, admitted, bytes, lattice)
+        inflight = collections.deque()
+        results = []
+        stream = self.pool.stream
+        t0 = time.perf_counter()
+        while pending or queue or active:
+            now = time.perf_counter() - t0
+            while pending and pending[0].arrival <= now:
+                queue.append(pending.popleft())
+            # admission: FIFO, by HBM budget and member slots
+            while queue:
+                spec = queue[0]
+                need = footprint(spec)
+                if need > self.budget or (self.screen and not stability.stable(spec.relax)):
+                    self.rejected.append(queue.popleft().tag)
+                    continue
+                if self.used + need > self.budget or len(active) >= self.max_members:
+                    break
+                queue.popleft()
+                lat = _new_lattice(spec, self.device, self.side)
+                self.pool.add(lat, spec.steps)
+                active[id(lat)] = (spec, time.perf_counter() - t0, need, lat)
+                self.used += need
+                self.peak_used = max(self.peak_used, self.used)
+                self.peak_members = max(self.peak_members, len(active))
+            running = [a for a in active.values() if self.pool.remaining(a[3]) > 0]
+            if running:
+                bps = sum(72 * a[0].nx * a[0].ny * STORE_BYTES[a[0].storage] / 4 for a in running)
+                self.pool.step(self._chunk_steps(bps))
+                ev = torch.cuda.Event()
+                ev.record(stream)
+                inflight.append(ev)
+                while len(inflight) > 2:
+                    inflight.popleft().synchronize()
+            finished = self.pool.poll(wait=not running and bool(active))
+            for lat in finished:
+                spec, admitted, need, _ = active.pop(id(lat))
+                status, diag = lat.diagnostics()
+                done = time.perf_counter() - t0
+                results.append(JobResult(spec.tag, spec.arrival, admitted, done, spec.nx, spec.ny, spec.steps,
+                                         spec.storage, diag, status))
+                lat.close()
+                self.used -= need
+            if not active and not queue and pending:
+                wait = pending[0].arrival - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+        return results
+
+    def close(self):
+        self.pool.close()
+
+
+def run_plain(trace, device="cuda:0") -> List[JobResult]:
+    """One job at a time in arrival order, one plain launch per step."""
+    results = []
+    t0 = time.perf_counter()
+    for spec in sorted(trace, key=lambda s: s.arrival):
+        now = time.perf_counter() - t0
+        if spec.arrival > now:
+            time.sleep(spec.arrival - now)
+        admitted = time.perf_counter() - t0
+        lat = _new_lattice(spec, device)
+        lat.step(spec.steps)
+        status, diag = lat.diagnostics()
+        done = time.perf_counter() - t0
+        results.append(JobResult(spec.tag, spec.arrival, admitted, done, spec.nx, spec.ny, spec.steps,
+                                 spec.storage, diag, status))
+        lat.close()
+    return results
+
+
+def summarize(results: List[JobResult]):
+    lat = [r.latency for r in results]
+    lups = sum(r.nx * r.ny * r.steps for r in results)
+    span = max(r.done for r in results) - min(r.arrival for r in results) if results else float("nan")
+    return {"jobs": len(results), "p50_s": round(percentile(lat, 50), 4), "p99_s": round(percentile(lat, 99), 4),
+            "mean_s": round(sum(lat) / max(1, len(lat)), 4), "makespan_s": round(span, 4),
+            "aggregate_mlups": round(lups / span / 1e6, 1) if span > 0 else None,
+            "nonfinite_jobs": sum(1 for r in results if r.status != 0)}
