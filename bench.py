@@ -32,14 +32,16 @@ METRIC = "MLUPS & % HBM roofline (D2Q9 MRT, 1 GPU); served p50/p99 vs plain at e
 STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 
 
+KERNEL_SOURCES = ("lbm_device.hpp", "lbm_kernels.hip")     # the files that define the device code
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1107_4543_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(name.encode())
-                h.update(fh.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
     return h.hexdigest()
 
 
@@ -153,7 +155,7 @@ def bench_batch256(args):
         for lat, f in zip(lats, fields):
             lat.init(*f)
 
-    pool = Pool(max_members=len(specs), max_tiles=1 << 17, device=dev)
+    pool = Pool(max_members=len(specs), max_tiles=1 << 18, device=dev)
     init_all()
     for lat in lats:
         pool.add(lat, steps)
@@ -221,14 +223,18 @@ def bench_serve(args):
     budget = int(args.budget_gb * 1e9)
     for i, rate in enumerate(float(r) for r in args.rates.split(",")):
         trace = lbm_inputs.serving_trace(100 + i, rate, args.jobs, accept=stability.stable)
-        srv = Server(budget, max_members=256)
+        srv = Server(budget, max_members=256, policy="sjf")
         served = srv.run(trace)
         srv.close()
+        fifo = Server(budget, max_members=256, policy="fifo")
+        served_fifo = fifo.run(trace)
+        fifo.close()
         plain = run_plain(trace)
         pd = {r.tag: r.diag for r in plain}
-        equal = all(r.diag == pd[r.tag] for r in served)
+        equal = all(r.diag == pd[r.tag] for r in served + served_fifo)
         row = {"rate_jobs_per_s": rate, "jobs": len(trace), "served": summarize(served),
-               "plain": summarize(plain), "equal_results": bool(equal), "rejected": len(srv.rejected),
+               "served_fifo": summarize(served_fifo), "plain": summarize(plain),
+               "equal_results": bool(equal), "rejected": len(srv.rejected),
                "peak_members": srv.peak_members, "peak_budget_gb": round(srv.peak_used / 1e9, 2)}
         out.append(row)
         print(json.dumps({"progress": row}), file=sys.stderr, flush=True)

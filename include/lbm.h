@@ -219,8 +219,9 @@ LBM_API lbm_status lbm_time_launches(lbm_lattice *lat, int32_t n, double *avg_us
 /* ---- pools: many lattices advanced together ------------------------------
  *
  * A pool advances its members (lattices of any size, rates and storage)
- * with one persistent launch per storage class and step; the step loop is
- * recorded once as a HIP graph of graph_steps steps and replayed.  Each
+ * with one persistent launch per storage class and step; step loops of
+ * power-of-two lengths up to graph_steps are recorded once as HIP graphs and
+ * replayed (lbm_pool_step(n) runs n steps as a few such replays).  Each
  * member carries its own step count: a member added with nsteps stops after
  * exactly nsteps steps, independently of the others, and is then returned by
  * lbm_pool_poll.  Members join and leave between lbm_pool_step calls
@@ -240,7 +241,8 @@ typedef struct lbm_pool lbm_pool;
  *                max(1, tile_cells / nx) rows), 64 .. 2^22
  *   block        threads per workgroup, multiple of 64, 64 .. 1024
  *   grid         workgroups of the persistent launch, 1 .. 2^20
- *   graph_steps  steps recorded in one graph replay, 1 .. 1024 */
+ *   graph_steps  longest recorded step loop (rounded down to a power of
+ *                two when used), 1 .. 1024 */
 typedef struct lbm_pool_shape {
     int32_t tile_cells;
     int32_t block;

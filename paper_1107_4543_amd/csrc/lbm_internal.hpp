@@ -64,9 +64,11 @@ struct PoolMember {
     int32_t cls, pad;
 };
 
-// A tile: nrows whole rows of one member, starting at row y0.
+// A tile of one member: rows y0 .. y0+nrows-1, columns x0 .. x0+ncols-1
+// (whole rows when the lattice is narrower than the tile size, otherwise a
+// segment of one row).
 struct PoolTile {
-    int32_t member, y0, nrows, pad;
+    int32_t member, y0, x0, nrows, ncols, pad0, pad1, pad2;
 };
 
 struct PoolHeader {

@@ -310,9 +310,10 @@ __global__ void __launch_bounds__(1024) k_step_vec(StepArgs<C> a)
 //
 // One launch advances every active member of one storage class by one step.
 // The grid is persistent (a fixed number of workgroups strides over the tile
-// table), so the same launch serves any membership.  A tile is nrows whole
-// rows of one member; its cells are walked as a flattened (row, x) index so
-// narrow lattices still fill whole waves.  Member k is active in launch k of
+// table), so the same launch serves any membership.  A tile is a rectangle
+// of one member (whole rows of a narrow lattice, a row segment of a wide
+// one); its cells are walked as a flattened (row, column) index so narrow
+// lattices still fill whole waves.  Member k is active in launch k of
 // a chunk while t_done + k < t_target; its source buffer alternates with
 // t_done + k.  The per-cell work is the same gather9 / cell_update / store9
 // as the single-lattice kernels, so a lattice gives bit-identical results
@@ -344,10 +345,11 @@ __global__ void __launch_bounds__(1024) k_pool_step(const PoolHeader *hdr, const
         const int64_t P = m->plane;
         const Relax<C> r = member_relax<C>(m);
         const float scale = m->scale, inv_scale = m->inv_scale;
-        const int ncell = tile.nrows * nx;
+        const int ncols = tile.ncols;
+        const int ncell = tile.nrows * ncols;
         for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
-            const int dy = c / nx;
-            const int x = c - dy * nx;
+            const int dy = c / ncols;
+            const int x = tile.x0 + (c - dy * ncols);
             const int y = tile.y0 + dy;
             const int xm = (x == 0 ? nx : x) - 1;
             const int xp = (x + 1 == nx) ? 0 : x + 1;

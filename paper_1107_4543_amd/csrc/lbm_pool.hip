@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -72,24 +73,33 @@ struct lbm_pool {
     bool dirty = true;
     unsigned class_mask = 0;         // classes with tiles in the uploaded tables
     int ntiles = 0;
-    lbm_pool_shape shape{4096, 256, 2048, 32};
+    int max_class_tiles = 0;         // largest tile range of one class
+    lbm_pool_shape shape{256, 512, 65536, 256};
     std::vector<Slot> slots;
     std::vector<int> finishing;      // slot indices in completion order
-    std::map<unsigned, GraphEntry> graphs;
+    std::map<std::tuple<unsigned, int, int>, GraphEntry> graphs;   // (class mask, steps, grid)
 };
 
 namespace {
 
+// Lattices narrower than the tile size are cut into bands of whole rows;
+// rows longer than max(tile_cells, 1024) cells are cut into segments.
 int tile_rows(const lbm_pool_shape &sh, const lbm_lattice *L)
 {
     int r = sh.tile_cells / std::max(1, L->v.nx);
     return std::max(1, std::min(r, L->v.ny));
 }
 
+int tile_cols(const lbm_pool_shape &sh, const lbm_lattice *L)
+{
+    const int seg = std::max(sh.tile_cells, 1024);
+    return L->v.nx <= seg ? L->v.nx : seg;
+}
+
 int tiles_of(const lbm_pool_shape &sh, const lbm_lattice *L)
 {
-    const int r = tile_rows(sh, L);
-    return (L->v.ny + r - 1) / r;
+    const int r = tile_rows(sh, L), c = tile_cols(sh, L);
+    return ((L->v.ny + r - 1) / r) * ((L->v.nx + c - 1) / c);
 }
 
 void drop_graphs(lbm_pool *P)
@@ -140,17 +150,19 @@ lbm_status upload(lbm_pool *P)
         m.inv_scale = (float)L->v.inv_scale;
         m.cls = class_of(L);
         if (s.t_done >= s.t_target) continue;        // finished: no tiles
-        const int r = tile_rows(P->shape, L);
-        for (int y0 = 0; y0 < L->v.ny; y0 += r) {
-            T t;
-            t.cls = m.cls;
-            t.t.member = i;
-            t.t.y0 = y0;
-            t.t.nrows = std::min(r, L->v.ny - y0);
-            t.t.pad = 0;
-            t.cells = (int64_t)t.t.nrows * L->v.nx;
-            all.push_back(t);
-        }
+        const int r = tile_rows(P->shape, L), cw = tile_cols(P->shape, L);
+        for (int y0 = 0; y0 < L->v.ny; y0 += r)
+            for (int x0 = 0; x0 < L->v.nx; x0 += cw) {
+                T t{};
+                t.cls = m.cls;
+                t.t.member = i;
+                t.t.y0 = y0;
+                t.t.x0 = x0;
+                t.t.nrows = std::min(r, L->v.ny - y0);
+                t.t.ncols = std::min(cw, L->v.nx - x0);
+                t.cells = (int64_t)t.t.nrows * t.t.ncols;
+                all.push_back(t);
+            }
     }
     if ((int)all.size() > P->max_tiles) return pfail(LBM_E_NOMEM, "pool needs %zu tiles, has %d", all.size(), P->max_tiles);
     // group by class, largest tiles first (balances the strided persistent grid)
@@ -167,6 +179,8 @@ lbm_status upload(lbm_pool *P)
         mask |= 1u << c;
     }
     P->ntiles = (int)all.size();
+    P->max_class_tiles = 0;
+    for (int c = 0; c < lbm::kClasses; ++c) P->max_class_tiles = std::max(P->max_class_tiles, hdr->end[c] - hdr->begin[c]);
     const size_t used = (size_t)((char *)P->d_tiles - P->ws) + sizeof(lbm::PoolTile) * all.size();
     if ((e = hipMemcpyAsync(P->ws, P->stage, used, hipMemcpyHostToDevice, P->stream)) != hipSuccess)
         return phip(e, "hipMemcpyAsync (pool tables)");
@@ -177,10 +191,22 @@ lbm_status upload(lbm_pool *P)
     return LBM_OK;
 }
 
-// Records the step loop of `steps` launches per class in `mask`, then commit.
-lbm_status get_graph(lbm_pool *P, unsigned mask, hipGraphExec_t *out)
+// Workgroups per launch: the shape's grid, or fewer when the tables hold
+// fewer tiles (rounded up to a power of two so that few graphs are needed).
+int launch_grid(const lbm_pool *P)
 {
-    auto it = P->graphs.find(mask);
+    int g = 1;
+    while (g < P->max_class_tiles && g < P->shape.grid) g *= 2;
+    return std::min(g, P->shape.grid);
+}
+
+// Records a step loop of `len` steps (one launch per class in `mask` and
+// step, each step depending on the previous one), then the commit kernel.
+lbm_status get_graph(lbm_pool *P, unsigned mask, int len, hipGraphExec_t *out)
+{
+    const int grid = launch_grid(P);
+    auto key = std::make_tuple(mask, len, grid);
+    auto it = P->graphs.find(key);
     if (it != P->graphs.end()) {
         *out = it->second.exec;
         return LBM_OK;
@@ -192,7 +218,7 @@ lbm_status get_graph(lbm_pool *P, unsigned mask, hipGraphExec_t *out)
     const lbm::PoolHeader *hdr = P->d_hdr;
     const lbm::PoolMember *mem = P->d_mem;
     const lbm::PoolTile *tiles = P->d_tiles;
-    for (int k = 0; k < P->shape.graph_steps; ++k) {
+    for (int k = 0; k < len; ++k) {
         cur.clear();
         for (int c = 0; c < lbm::kClasses; ++c) {
             if (!(mask & (1u << c))) continue;
@@ -200,7 +226,7 @@ lbm_status get_graph(lbm_pool *P, unsigned mask, hipGraphExec_t *out)
             void *args[] = {(void *)&hdr, (void *)&mem, (void *)&tiles, (void *)&cls, (void *)&kk};
             hipKernelNodeParams np{};
             np.func = lbm::pool_step_kernel(c);
-            np.gridDim = dim3(P->shape.grid);
+            np.gridDim = dim3(grid);
             np.blockDim = dim3(P->shape.block);
             np.sharedMemBytes = 0;
             np.kernelParams = args;
@@ -216,7 +242,7 @@ lbm_status get_graph(lbm_pool *P, unsigned mask, hipGraphExec_t *out)
         prev.swap(cur);
     }
     lbm::PoolMember *memw = P->d_mem;
-    int nmem = P->max_members, kk = P->shape.graph_steps;
+    int nmem = P->max_members, kk = len;
     void *cargs[] = {(void *)&memw, (void *)&nmem, (void *)&kk};
     hipKernelNodeParams cp{};
     cp.func = lbm::pool_commit_kernel();
@@ -233,31 +259,20 @@ lbm_status get_graph(lbm_pool *P, unsigned mask, hipGraphExec_t *out)
         (void)hipGraphDestroy(g.graph);
         return phip(e, "hipGraphInstantiate");
     }
-    P->graphs[mask] = g;
+    P->graphs[key] = g;
     *out = g.exec;
     return LBM_OK;
 }
 
-// Advances every active member by min(kk, remaining); kk <= graph_steps.
+// Advances every active member by min(kk, remaining) with one recorded loop
+// of kk steps; kk is a power of two <= graph_steps.
 lbm_status run_chunk(lbm_pool *P, int kk)
 {
     hipError_t e;
-    if (kk == P->shape.graph_steps) {
-        hipGraphExec_t ex;
-        lbm_status st = get_graph(P, P->class_mask, &ex);
-        if (st != LBM_OK) return st;
-        if ((e = hipGraphLaunch(ex, P->stream)) != hipSuccess) return phip(e, "hipGraphLaunch");
-    } else {
-        for (int k = 0; k < kk; ++k)
-            for (int c = 0; c < lbm::kClasses; ++c) {
-                if (!(P->class_mask & (1u << c))) continue;
-                if ((e = lbm::launch_pool_step(c, P->d_hdr, P->d_mem, P->d_tiles, k, P->shape.grid, P->shape.block,
-                                               P->stream)) != hipSuccess)
-                    return phip(e, "pool step launch");
-            }
-        if ((e = lbm::launch_pool_commit(P->d_mem, P->max_members, kk, P->stream)) != hipSuccess)
-            return phip(e, "pool commit launch");
-    }
+    hipGraphExec_t ex;
+    lbm_status st = get_graph(P, P->class_mask, kk, &ex);
+    if (st != LBM_OK) return st;
+    if ((e = hipGraphLaunch(ex, P->stream)) != hipSuccess) return phip(e, "hipGraphLaunch");
     for (int i = 0; i < P->max_members; ++i) {
         Slot &s = P->slots[i];
         if (!s.lat || s.finishing) continue;
@@ -428,7 +443,10 @@ lbm_status lbm_pool_step(lbm_pool *pool, int64_t nsteps)
         if (max_rem == 0) break;
         lbm_status st = upload(pool);
         if (st != LBM_OK) return st;
-        const int kk = (int)std::min<int64_t>({nsteps, (int64_t)pool->shape.graph_steps, max_rem});
+        // the longest recorded loop (a power of two) that fits
+        const int64_t lim = std::min<int64_t>({nsteps, (int64_t)pool->shape.graph_steps, max_rem});
+        int kk = 1;
+        while ((int64_t)kk * 2 <= lim) kk *= 2;
         if ((st = run_chunk(pool, kk)) != LBM_OK) return st;
         nsteps -= kk;
         // finished members keep their (now idle) tiles until the next upload
@@ -525,7 +543,7 @@ lbm_status lbm_pool_time_launches(lbm_pool *pool, int32_t reps, double *avg_us)
     auto launch_all = [&]() -> hipError_t {
         for (int c = 0; c < lbm::kClasses; ++c) {
             if (!(pool->class_mask & (1u << c))) continue;
-            hipError_t r = lbm::launch_pool_step(c, pool->d_hdr, pool->d_mem, pool->d_tiles, 0, pool->shape.grid,
+            hipError_t r = lbm::launch_pool_step(c, pool->d_hdr, pool->d_mem, pool->d_tiles, 0, launch_grid(pool),
                                                  pool->shape.block, pool->stream);
             if (r != hipSuccess) return r;
         }
@@ -551,9 +569,9 @@ lbm_status lbm_pool_tune(lbm_pool *pool, int32_t reps, lbm_pool_shape *best, dou
     const lbm_pool_shape keep = pool->shape;
     lbm_pool_shape best_s = keep;
     double best_t = INFINITY;
-    for (int cells : {1024, 2048, 4096, 8192, 16384})
+    for (int cells : {256, 512, 1024, 2048, 4096, 16384})
         for (int block : {256, 512, 1024})
-            for (int grid : {1024, 2048, 4096}) {
+            for (int grid : {1024, 4096, 16384, 65536, 262144}) {
                 lbm_pool_shape s = keep;
                 s.tile_cells = cells;
                 s.block = block;

@@ -61,7 +61,7 @@ class Pool:
     def shape(self):
         return _lib.lbm_pool_get_shape(self._h).as_dict()
 
-    def set_shape(self, tile_cells=4096, block=256, grid=2048, graph_steps=32):
+    def set_shape(self, tile_cells=256, block=512, grid=65536, graph_steps=256):
         _lib.lbm_pool_set_shape(self._h, _lib.lbm_pool_shape(tile_cells, block, grid, graph_steps))
         return self
 

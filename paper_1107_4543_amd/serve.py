@@ -88,13 +88,22 @@ def percentile(xs, q):
 
 
 class Server:
-    def __init__(self, hbm_budget_bytes, max_members=256, max_tiles=1 << 18, chunk_ms=10.0,
-                 device="cuda:0", screen=False, tune=False):
+    """policy: "sjf" admits the queued job with the least work (cells x steps)
+    first, "fifo" in arrival order.  max_active_cells caps the cells being
+    advanced at once (enough to fill the GPU; more only stretches every job's
+    latency), in addition to the HBM budget and the member slots."""
+
+    def __init__(self, hbm_budget_bytes, max_members=256, max_tiles=1 << 20, chunk_ms=10.0,
+                 device="cuda:0", screen=False, tune=False, policy="sjf", max_active_cells=1 << 25,
+                 tile_cells=512):
         self.device = torch.device(device)
         self.budget = int(hbm_budget_bytes)
         self.pool = Pool(max_members=max_members, max_tiles=max_tiles, device=self.device)
+        self.pool.set_shape(tile_cells=tile_cells, block=512, grid=65536, graph_steps=256)
         self.max_members = max_members
         self.chunk_ms = chunk_ms
+        self.policy = policy
+        self.max_active_cells = max_active_cells
         self.screen = screen
         self.tune = tune
         self.used = 0
@@ -107,8 +116,9 @@ class Server:
         self.side = torch.cuda.Stream(self.device)
 
     def _chunk_steps(self, active_bytes_per_step):
-        est_ms = active_bytes_per_step / (HBM_GBPS_ESTIMATE * 1e6)
-        return max(1, min(self.pool.shape["graph_steps"], int(self.chunk_ms / max(est_ms, 1e-6))))
+        # about chunk_ms of device work; short steps are bounded below by launch cost
+        est_ms = max(active_bytes_per_step / (HBM_GBPS_ESTIMATE * 1e6), 0.004)
+        return max(1, min(1024, int(self.chunk_ms / est_ms)))
 
     def run(self, trace) -> List[JobResult]:
         pending = collections.deque(sorted(trace, key=lambda s: s.arrival))
@@ -122,18 +132,28 @@ class Server:
             now = time.perf_counter() - t0
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
-            # admission: FIFO, by HBM budget and member slots
+            # admission by HBM budget, member slots and the active-cells cap
+            if self.policy == "sjf" and len(queue) > 1:
+                queue = collections.deque(sorted(queue, key=lambda s: s.nx * s.ny * s.steps))
             while queue:
                 spec = queue[0]
                 need = footprint(spec)
                 if need > self.budget or (self.screen and not stability.stable(spec.relax)):
                     self.rejected.append(queue.popleft().tag)
                     continue
-                if self.used + need > self.budget or len(active) >= self.max_members:
+                active_cells = sum(a[0].nx * a[0].ny for a in active.values())
+                if (self.used + need > self.budget or len(active) >= self.max_members
+                        or (active and active_cells + spec.nx * spec.ny > self.max_active_cells)):
+                    break
+                lat = _new_lattice(spec, self.device, self.side)
+                try:
+                    self.pool.add(lat, spec.steps)
+                except _lib.LbmError as e:
+                    if e.status != _lib.LBM_E_NOMEM or not active:
+                        raise
+                    lat.close()                      # tile table full: retry when a job leaves
                     break
                 queue.popleft()
-                lat = _new_lattice(spec, self.device, self.side)
-                self.pool.add(lat, spec.steps)
                 active[id(lat)] = (spec, time.perf_counter() - t0, need, lat)
                 self.used += need
                 self.peak_used = max(self.peak_used, self.used)

@@ -74,7 +74,7 @@ def test_continuous_membership_and_remove():
     b, fb = make(50, 70, s, "f32", seed=2)
     c, fc = make(70, 20, s, "f64", seed=3)
     pool.add(a, 50)
-    pool.step(20)                                     # 2 graph replays + 4 direct steps
+    pool.step(20)                                     # recorded loops of 8, 8 and 4 steps
     pool.add(b, 30)                                   # joins while a is in flight
     with pytest.raises(_lib.LbmError) as e:
         a.step(1)
@@ -124,7 +124,7 @@ def test_pool_tune_and_timing_leave_states_unchanged():
         pool.add(lat, 10)
         lats.append(lat)
     shape, us = pool.tune(reps=2)
-    assert us > 0 and shape["tile_cells"] >= 1024
+    assert us > 0 and shape["tile_cells"] >= 256
     pool.time_launches(2)
     for lat in lats:
         pool.remove(lat)
@@ -144,7 +144,7 @@ def test_full_batch_of_256_lattices_matches_alone_on_a_sample():
     from paper_1107_4543_amd.pool import Pool
     w = lbm_inputs.WORKLOADS["batch256"]
     specs = lbm_inputs.batch_specs(w["seed"], w["count"], steps=w["steps"], accept=stability.stable)
-    pool = Pool(max_members=256, max_tiles=1 << 16)
+    pool = Pool(max_members=256, max_tiles=1 << 18)
     lats = []
     for sp in specs:
         lat = Lattice(sp.nx, sp.ny, *stability.rates(sp.relax), storage="f32", device="cuda:0")
