@@ -247,6 +247,62 @@ def bench_serve(args):
             "serving": out}
 
 
+def bench_pulses8192(args):
+    """Precision study: 8192 x 8192, Lallemand-Luo rates (nu = 1e-3), 16 seeded
+    Gaussian pulses, 1000 steps, for each storage type (FP64 with FP64 and
+    with FP32 collide, FP32, FP16, BF16 with FP32 collide): MLUPS and roofline
+    of the tuned step kernel, and the density error against the FP64 run
+    (which the tests check against the oracle on sampled windows)."""
+    import torch
+
+    import lbm_inputs
+    from paper_1107_4543_amd import Lattice
+    w = lbm_inputs.WORKLOADS["pulses8192"]
+    nx, ny = w["nx"], w["ny"]
+    T = w["steps"] if args.steps == 2000 else args.steps
+    ll = lbm_inputs.PRESETS["LL"]
+    s = [ll["s_e"], ll["s_eps"], ll["s_q"], 1.0 / (3.0 * w["nu"] + 0.5)]
+    specs = lbm_inputs.random_pulse_specs(nx, ny, w["seed"], w["count"])
+    dev = "cuda:0"
+    fields = lbm_inputs.pulses_field_torch(nx, ny, specs, dev)
+    A = float((fields[0] - 1.0).abs().max())
+    rows, rho_ref = [], None
+    for storage, compute in [("f64", "f64"), ("f64", "f32"), ("f32", "f32"), ("f16", "f32"), ("bf16", "f32")]:
+        lat = Lattice(nx, ny, *s, storage=storage, compute=compute, device=dev).init(*fields)
+        launch, _ = lat.tune(reps=3)
+        lat.init(*fields)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(lat.stream)
+        lat.step(T)
+        e1.record(lat.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        rho = lat.moments()[0]
+        if rho_ref is None:
+            rho_ref = rho
+            e_inf = e_l2 = 0.0
+        else:
+            d = rho - rho_ref
+            e_inf = float(d.abs().max()) / A
+            e_l2 = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(rho_ref - 1.0))
+        bpl = 18 * STORE_BYTES[storage]
+        gbps = bpl * nx * ny * T / (ms / 1e3) / 1e9
+        rows.append({"storage": storage, "compute": compute, "mlups": round(nx * ny * T / (ms / 1e3) / 1e6, 1),
+                     "bytes_per_lu": bpl, "achieved_GBps": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                     "launch": launch, "scale_exp": lat.scale_exp,
+                     "linf_err_over_A": e_inf, "l2_rel_err": e_l2})
+        print(json.dumps({"progress": rows[-1]}), file=sys.stderr, flush=True)
+        del lat, rho
+    best = max(rows, key=lambda r: r["mlups"])
+    return {"metric": METRIC, "value": best["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": T, "warmup": 0,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": best["storage"],
+            "data": "synthetic",
+            "config": {"workload": "pulses8192", "nx": nx, "ny": ny, "pulses": w["count"], "seed": w["seed"],
+                       "relaxation": "Lallemand-Luo, nu = 1e-3", "amplitude_max": A},
+            "precision": rows}
+
+
 def parse_launch(text):
     keys = ["variant", "block_x", "block_y", "rows", "xcd_remap", "flags"]
     vals = [int(v) for v in text.split(",")]
@@ -261,7 +317,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16", "bf16"])
-    ap.add_argument("--workload", default="waves4096", choices=["waves4096", "batch256", "serve"],
+    ap.add_argument("--workload", default="waves4096", choices=["waves4096", "batch256", "serve", "pulses8192"],
                     help="waves4096: one 4096^2 lattice (default); batch256: 256 lattices, pool vs "
                          "sequential; serve: Poisson job traces, continuous batching vs plain FIFO")
     ap.add_argument("--rates", default="10,30,100,300,1000", help="serve: arrival rates (jobs/s)")
@@ -293,6 +349,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps(bench_serve(args)), flush=True)
+        return
+    if args.workload == "pulses8192":
+        print(json.dumps(bench_pulses8192(args)), flush=True)
         return
 
     lat, cfg, rates, fields1, w = build_waves4096(args.storage)

@@ -147,6 +147,37 @@ def pulses_field(nx: int, ny: int, specs: List[PulseSpec], rho0: float = 1.0,
     return rho, z, z.copy()
 
 
+def pulses_field_torch(nx: int, ny: int, specs: List[PulseSpec], device, rho0: float = 1.0):
+    """``pulses_field`` generated on a torch device (float64)."""
+    import torch
+    x = torch.arange(nx, dtype=torch.float64, device=device)[None, :]
+    y = torch.arange(ny, dtype=torch.float64, device=device)[:, None]
+    rho = torch.full((ny, nx), rho0, dtype=torch.float64, device=device)
+    for p in specs:
+        dx = x - p.cx
+        dx = dx - nx * torch.round(dx / nx)
+        dy = y - p.cy
+        dy = dy - ny * torch.round(dy / ny)
+        rho += p.amplitude * torch.exp(-math.log(2.0) * (dx * dx + dy * dy) / (p.half_width ** 2))
+    z = torch.zeros_like(rho)
+    return rho, z, z.clone()
+
+
+def pulses_window(nx: int, ny: int, specs: List[PulseSpec], x0: int, y0: int, w: int, rho0: float = 1.0):
+    """The fields of ``pulses_field`` on a w x w window of the periodic
+    nx x ny lattice whose corner is cell (x0, y0): entry [i, j] is cell
+    ((x0 + j) mod nx, (y0 + i) mod ny)."""
+    x = ((x0 + np.arange(w)) % nx).astype(np.float64)[None, :]
+    y = ((y0 + np.arange(w)) % ny).astype(np.float64)[:, None]
+    rho = np.full((w, w), rho0)
+    for p in specs:
+        dx = _min_image(x - p.cx, nx)
+        dy = _min_image(y - p.cy, ny)
+        rho += p.amplitude * np.exp(-math.log(2.0) * (dx * dx + dy * dy) / (p.half_width ** 2))
+    z = np.zeros_like(rho)
+    return rho, z, z.copy()
+
+
 def random_pulses(nx: int, ny: int, seed: int, count: int = 16,
                   amp_range=(1e-5, 1e-3), width_range=(3.0, 12.0)):
     """Sum of ``count`` seeded Gaussian pulses on rho0 = 1, u = 0."""

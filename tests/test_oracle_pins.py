@@ -249,3 +249,40 @@ def test_table3_sigma_form_equals_table5_rates():
         for k in ("e", "nu", "eps", "q"):
             s = float(linear.s_from_sigma(t3["sigma_" + k]))
             assert abs(s - t5["s_" + k]) < 1e-8, (g, k)
+
+
+def test_window_run_reproduces_the_centre_of_a_larger_periodic_run():
+    # A cell's value after T steps depends only on cells within distance T,
+    # so an oracle run on a periodic window of side 2T + 1 + 2r reproduces the
+    # central (2r + 1)^2 block of the run on the whole lattice exactly (the
+    # basis of the sampled full-size parity checks).
+    import lbm_inputs
+    nx = ny = 64
+    T, r = 9, 2
+    specs = lbm_inputs.random_pulse_specs(nx, ny, seed=5, count=6, width_range=(2.0, 5.0))
+    full = oracle.run(oracle.init(*lbm_inputs.pulses_field(nx, ny, specs)), ll_rates(), T)
+    w = 2 * T + 1 + 2 * r
+    x0, y0 = 50, 3                                   # window wraps around the lattice edge
+    win = oracle.run(oracle.init(*lbm_inputs.pulses_window(nx, ny, specs, x0, y0, w)), ll_rates(), T)
+    c = slice(T, T + 2 * r + 1)
+    ys = (y0 + np.arange(w))[c] % ny
+    xs = (x0 + np.arange(w))[c] % nx
+    assert np.array_equal(win[:, c, c], full[:, ys][:, :, xs])
+    # a window two cells too small (side 2T - 1) around the same centre cell
+    # lets wrapped values reach it, and the centre then differs
+    gx, gy = (x0 + T + r) % nx, (y0 + T + r) % ny
+    small = oracle.run(oracle.init(*lbm_inputs.pulses_window(nx, ny, specs, gx - (T - 1), gy - (T - 1),
+                                                              2 * T - 1)), ll_rates(), T)
+    assert np.array_equal(win[:, T + r, T + r], full[:, gy, gx])
+    assert not np.array_equal(small[:, T - 1, T - 1], full[:, gy, gx])
+
+
+def test_unstable_relaxation_set_blows_up_in_the_oracle():
+    # A set outside the von Neumann stability region (max |lambda| = 1.14 at
+    # the checkerboard mode) must blow up; the linear analysis predicts it.
+    import lbm_inputs
+    s = [1.860, 1.075, 1.312, 1.9169]
+    assert linear.spectral_radius(*s, nk=16) > 1.1
+    rho, ux, uy = lbm_inputs.gaussian_pulse(64, 64, 1e-3, 4.0)
+    f = oracle.run(oracle.init(rho, ux, uy), s, 600)
+    assert not np.all(np.isfinite(f)) or np.max(np.abs(f)) > 1e3
