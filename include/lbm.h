@@ -67,7 +67,9 @@ typedef int32_t lbm_status;
 
 /*
  * Lattice descriptor.
- *   nx, ny      lattice size, >= 1 each, nx * ny < 2^31.
+ *   nx, ny      lattice size, >= 1 each; with pitch = nx rounded up to 64,
+ *               pitch * ny < 2^31 and pitch * ny * sizeof(storage) < 2^32
+ *               (one population plane below 4 GiB).
  *   storage     LBM_STORE_*.  The library stores the deviation
  *               g_i = (f_i - f^eq_i(rho0, u0)) * 2^scale_exp, i.e. the
  *               fluctuating part about the uniform state (Sec. 4.1, Eq.
@@ -104,7 +106,10 @@ typedef struct lbm_lattice lbm_lattice;
  *             loads, x-shift by cross-lane exchange; needs nx % 2^variant == 0
  *             and block_x % 64 == 0),
  *             4 = one cell per lane, each workgroup walks whole rows in chunks
- *             of block_x cells (row strips)
+ *             of block_x cells (row strips),
+ *             5, 6, 7 = 2, 4, 8 consecutive cells per lane, x-shifted values
+ *             taken from overlapping aligned vector loads (needs
+ *             nx % 2^(variant-4) == 0)
  *   block_x   lanes along x per workgroup, block_y rows per workgroup pass;
  *             64 <= block_x * block_y <= 1024
  *   rows      rows each lane processes, 1..64 (tile height = block_y * rows)
@@ -112,7 +117,7 @@ typedef struct lbm_lattice lbm_lattice;
  *             same XCD (shared L2), 0 = hardware order
  *   flags     bit 0: non-temporal loads; bit 1: issue the next row's (variant
  *             0) or next chunk's (variant 4) loads before colliding the current
- *             cells.
+ *             cells (variants 0 and 4 only).
  * Every shape produces bit-identical results. */
 typedef struct lbm_launch {
     int32_t variant;

@@ -55,6 +55,8 @@ lbm_status validate(const lbm_desc *d)
     if (pitch * (int64_t)d->ny >= ((int64_t)1 << 31))
         return fail(LBM_E_INVAL, "lattice too large: pitch * ny must be < 2^31");
     if (lbm::storage_bytes(d->storage) == 0) return fail(LBM_E_INVAL, "unknown storage %d", d->storage);
+    if ((uint64_t)pitch * (uint64_t)d->ny * lbm::storage_bytes(d->storage) >= ((uint64_t)1 << 32))
+        return fail(LBM_E_INVAL, "lattice too large: one population plane must be smaller than 4 GiB");
     if (d->compute != LBM_COMPUTE_F64 && d->compute != LBM_COMPUTE_F32)
         return fail(LBM_E_INVAL, "unknown compute %d", d->compute);
     if (d->compute == LBM_COMPUTE_F64 && d->storage != LBM_STORE_F64)
@@ -121,7 +123,7 @@ std::vector<lbm_launch> shape_candidates(const View &v)
 std::vector<lbm_launch> variant_candidates(const View &v, const lbm_launch &best)
 {
     std::vector<lbm_launch> out;
-    for (int var = 0; var < 5; ++var)
+    for (int var = 0; var < 8; ++var)
         for (int flags = 0; flags < 4; ++flags)
             for (int rows : {best.rows, 2 * best.rows}) {
                 lbm_launch c = best;
@@ -432,26 +434,53 @@ lbm_status lbm_tune(lbm_lattice *lat, int32_t reps, lbm_launch *best, double *be
     if (!lat || reps < 1) return fail(LBM_E_INVAL, "bad argument");
     if (!lat->initialized) return fail(LBM_E_STATE, "tune before init");
     if (lat->pool) return busy(lat);
-    double best_t = INFINITY;
-    lbm_launch best_c = lat->launch;
-    auto sweep = [&](const std::vector<lbm_launch> &cands) -> lbm_status {
+    struct Timed {
+        double us;
+        lbm_launch c;
+    };
+    auto sweep = [&](const std::vector<lbm_launch> &cands, int r, std::vector<Timed> &out) -> lbm_status {
         for (const lbm_launch &c : cands) {
             double us;
-            lbm_status st = time_shape(lat, c, reps, &us);
+            lbm_status st = time_shape(lat, c, r, &us);
             if (st != LBM_OK) return st;
-            if (us < best_t) {
-                best_t = us;
-                best_c = c;
-            }
+            out.push_back({us, c});
         }
+        std::sort(out.begin(), out.end(), [](const Timed &a, const Timed &b) { return a.us < b.us; });
         return LBM_OK;
     };
-    lbm_status st = sweep(shape_candidates(lat->v));
-    if (st == LBM_OK) st = sweep(variant_candidates(lat->v, best_c));
+    auto same = [](const lbm_launch &a, const lbm_launch &b) {
+        return a.variant == b.variant && a.block_x == b.block_x && a.block_y == b.block_y && a.rows == b.rows &&
+               a.xcd_remap == b.xcd_remap && a.flags == b.flags;
+    };
+    // stage 1: workgroup shapes of the one-cell kernel
+    std::vector<Timed> s1;
+    lbm_status st = sweep(shape_candidates(lat->v), reps, s1);
     if (st != LBM_OK) return st;
-    lat->launch = best_c;
-    if (best) *best = best_c;
-    if (best_us) *best_us = best_t;
+    // stage 2: every variant and flag combination around the three best shapes
+    std::vector<lbm_launch> c2;
+    for (size_t k = 0; k < s1.size() && k < 3; ++k)
+        for (const lbm_launch &c : variant_candidates(lat->v, s1[k].c)) {
+            bool dup = false;
+            for (const lbm_launch &d : c2) dup = dup || same(c, d);
+            if (!dup) c2.push_back(c);
+        }
+    std::vector<Timed> s2 = s1;
+    if ((st = sweep(c2, reps, s2)) != LBM_OK) return st;
+    // final: re-time the six best with more launches, twice, keep the minimum
+    std::vector<Timed> fin;
+    for (size_t k = 0; k < s2.size() && fin.size() < 6; ++k) {
+        bool dup = false;
+        for (const Timed &d : fin) dup = dup || same(s2[k].c, d.c);
+        if (dup) continue;
+        double a, b;
+        if ((st = time_shape(lat, s2[k].c, 4 * reps, &a)) != LBM_OK) return st;
+        if ((st = time_shape(lat, s2[k].c, 4 * reps, &b)) != LBM_OK) return st;
+        fin.push_back({std::min(a, b), s2[k].c});
+    }
+    std::sort(fin.begin(), fin.end(), [](const Timed &a, const Timed &b) { return a.us < b.us; });
+    lat->launch = fin.front().c;
+    if (best) *best = fin.front().c;
+    if (best_us) *best_us = fin.front().us;
     return LBM_OK;
 }
 

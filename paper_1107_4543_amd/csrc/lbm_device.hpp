@@ -81,45 +81,69 @@ __host__ __device__ __forceinline__ void back_transform(const T m[9], T f[9])
     f[8] = r + ex - ey + ed + qxd - qyd - pxy;
 }
 
+// Fused multiply-add written out (the library is built without automatic
+// contraction, so every kernel evaluates exactly these operations).
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// 1/x: the hardware reciprocal (about 1 ulp) in FP32, an IEEE division in FP64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 // The collision increment dg = g* - g of one cell in the compute type T.
+//
+// g may hold the deviations multiplied by 2^p (16-bit storage); t = 2^-p is
+// then applied only where the equilibrium is not homogeneous of degree one
+// (the |j|^2 terms and the density in the denominator), so that every
+// intermediate value is exactly 2^p times its unscaled counterpart and dg
+// comes out scaled by 2^p with the same rounding.
 template <typename T>
-__device__ __forceinline__ void collide_increment(const T g[9], const Relax<T> &r, T dg[9])
+__device__ __forceinline__ void collide_increment(const T g[9], const Relax<T> &r, T t, T dg[9])
 {
     // m' = M g
-    const T a = (g[1] + g[3]) + (g[2] + g[4]);          // axis sum
-    const T b = (g[5] + g[7]) + (g[6] + g[8]);          // diagonal sum
+    const T s13 = g[1] + g[3], s24 = g[2] + g[4];
+    const T s57 = g[5] + g[7], s68 = g[6] + g[8];
+    const T a = s13 + s24;                              // axis sum
+    const T b = s57 + s68;                              // diagonal sum
     const T rho = g[0] + a + b;
     const T dx1 = g[1] - g[3], dy1 = g[2] - g[4];
     const T d57 = g[5] - g[7], d86 = g[8] - g[6];
     const T dxd = d57 + d86;                            // sum_diag c_x g
     const T dyd = d57 - d86;                            // sum_diag c_y g
     const T jx = dx1 + dxd, jy = dy1 + dyd;
-    const T e = T(-4) * g[0] - a + T(2) * b;
-    const T eps = T(4) * g[0] - T(2) * a + b;
-    const T pxx = (g[1] + g[3]) - (g[2] + g[4]);
-    const T pxy = (g[5] + g[7]) - (g[6] + g[8]);
-    const T qx = T(-2) * dx1 + dxd, qy = T(-2) * dy1 + dyd;
-    // equilibrium deviation (one reciprocal), then (s_k / D_k)(dmeq_k - m'_k)
-    T dm[9];
-    delta_meq(rho, jx, jy, r, dm);
-    const T a3 = r.lam_e * (dm[3] - e);
-    const T a4 = r.lam_eps * (dm[4] - eps);
-    const T a5 = r.lam_q * (dm[5] - qx);
-    const T a6 = r.lam_q * (dm[6] - qy);
-    const T a7 = r.lam_nu * (dm[7] - pxx);
-    const T a8 = r.lam_nu * (dm[8] - pxy);
+    const T e = fmad(T(2), b, fmad(T(-4), g[0], -a));
+    const T eps = fmad(T(4), g[0], fmad(T(-2), a, b));
+    const T pxx = s13 - s24;
+    const T pxy = s57 - s68;
+    const T qx = fmad(T(-2), dx1, dxd), qy = fmad(T(-2), dy1, dyd);
+    // equilibrium deviation (Sec. 2.3) about (rho0, j0), one reciprocal
+    const T inv = recip(fmad(t, rho, r.rho0));
+    const T tjx = t * jx, tjy = t * jy;
+    const T dQ = fmad(-r.Q0, rho, fmad(T(2), fmad(r.j0x, jx, r.j0y * jy), fmad(tjx, jx, tjy * jy))) * inv;
+    const T dP = fmad(-r.P0, rho, fmad(T(2), fmad(r.j0x, jx, -(r.j0y * jy)), fmad(tjx, jx, -(tjy * jy)))) * inv;
+    const T dX = fmad(-r.X0, rho, fmad(r.j0x, jy, fmad(r.j0y, jx, tjx * jy))) * inv;
+    // (s_k / D_k) (dmeq_k - m'_k), k = 3..8
+    const T a3 = r.lam_e * (fmad(T(3), dQ, T(-2) * rho) - e);
+    const T a4 = r.lam_eps * (fmad(T(-3), dQ, rho) - eps);
+    const T a5 = r.lam_q * (-jx - qx);
+    const T a6 = r.lam_q * (-jy - qy);
+    const T a7 = r.lam_nu * (dP - pxx);
+    const T a8 = r.lam_nu * (dX - pxy);
     // dg = M^T a
-    const T A = -a3 - T(2) * a4;
-    const T B = T(2) * a3 + a4;
+    const T A = fmad(T(-2), a4, -a3);
+    const T B = fmad(T(2), a3, a4);
+    const T A7 = A + a7, Am7 = A - a7;
+    const T B8 = B + a8, Bm8 = B - a8;
+    const T p56 = a5 + a6, m56 = a5 - a6;
     dg[0] = T(4) * (a4 - a3);
-    dg[1] = A - T(2) * a5 + a7;
-    dg[2] = A - T(2) * a6 - a7;
-    dg[3] = A + T(2) * a5 + a7;
-    dg[4] = A + T(2) * a6 - a7;
-    dg[5] = B + a5 + a6 + a8;
-    dg[6] = B - a5 + a6 - a8;
-    dg[7] = B - a5 - a6 + a8;
-    dg[8] = B + a5 - a6 - a8;
+    dg[1] = fmad(T(-2), a5, A7);
+    dg[2] = fmad(T(-2), a6, Am7);
+    dg[3] = fmad(T(2), a5, A7);
+    dg[4] = fmad(T(2), a6, Am7);
+    dg[5] = B8 + p56;
+    dg[6] = Bm8 - m56;
+    dg[7] = B8 - p56;
+    dg[8] = Bm8 + m56;
 }
 
 // ---- storage types ---------------------------------------------------------

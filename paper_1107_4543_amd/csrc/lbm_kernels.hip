@@ -60,24 +60,19 @@ __device__ __forceinline__ int remap_xcd(int bid, int nb)
     return xcd * per + (xcd < rem ? xcd : rem) + local;
 }
 
-// Collide one cell held as widened stored values w (in place).
+// Collide one cell held as widened stored values w (in place).  16-bit
+// storage is collided in its scaled units (see collide_increment).
 template <typename S, typename C>
 __device__ __forceinline__ void cell_update(typename Store<S>::wide w[9], const Relax<C> &r,
-                                            float scale, float inv_scale)
+                                            float /*scale*/, float inv_scale)
 {
     using W = typename Store<S>::wide;
     C g[9], dg[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        if constexpr (Store<S>::scaled) w[i] *= (W)inv_scale;
-        g[i] = (C)w[i];
-    }
-    collide_increment<C>(g, r, dg);
+    for (int i = 0; i < 9; ++i) g[i] = (C)w[i];
+    collide_increment<C>(g, r, Store<S>::scaled ? (C)inv_scale : C(1), dg);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        w[i] = w[i] + (W)dg[i];
-        if constexpr (Store<S>::scaled) w[i] *= (W)scale;
-    }
+    for (int i = 0; i < 9; ++i) w[i] = w[i] + (W)dg[i];
 }
 
 // ---- fused step -------------------------------------------------------------
@@ -89,30 +84,43 @@ __device__ __forceinline__ typename Store<S>::wide ld(const typename Store<S>::r
     else return Store<S>::widen(*p);
 }
 
+// Addressing: plane i of a buffer starts at base + i * plane_bytes (a
+// wave-uniform pointer); within a plane a cell is a 32-bit byte offset
+// row * pitch_bytes + x * sizeof (planes are smaller than 4 GiB), which the
+// hardware adds to the uniform base in the load instruction itself.
+template <typename R>
+__device__ __forceinline__ const R *at(const char *base, uint32_t off)
+{
+    return (const R *)(base + off);
+}
+
 // The nine pulled values of cell (x, y): population i comes from x - v_i.
-// r0, rm, rp: offsets of rows y, y-1, y+1; xm, xp: columns x-1, x+1 (wrapped).
+// r0, rm, rp: byte offsets of rows y, y-1, y+1; c0, cm, cp: byte offsets of
+// columns x, x-1, x+1 (wrapped).
 template <typename S, bool NT>
-__device__ __forceinline__ void gather9(const typename Store<S>::raw *__restrict__ src, int64_t P, int64_t r0,
-                                        int64_t rm, int64_t rp, int x, int xm, int xp,
+__device__ __forceinline__ void gather9(const char *__restrict__ src, uint64_t pb, uint32_t r0, uint32_t rm,
+                                        uint32_t rp, uint32_t c0, uint32_t cm, uint32_t cp,
                                         typename Store<S>::wide w[9])
 {
-    w[0] = ld<S, NT>(src + 0 * P + r0 + x);
-    w[1] = ld<S, NT>(src + 1 * P + r0 + xm);
-    w[2] = ld<S, NT>(src + 2 * P + rm + x);
-    w[3] = ld<S, NT>(src + 3 * P + r0 + xp);
-    w[4] = ld<S, NT>(src + 4 * P + rp + x);
-    w[5] = ld<S, NT>(src + 5 * P + rm + xm);
-    w[6] = ld<S, NT>(src + 6 * P + rm + xp);
-    w[7] = ld<S, NT>(src + 7 * P + rp + xp);
-    w[8] = ld<S, NT>(src + 8 * P + rp + xm);
+    using R = typename Store<S>::raw;
+    w[0] = ld<S, NT>(at<R>(src + 0 * pb, r0 + c0));
+    w[1] = ld<S, NT>(at<R>(src + 1 * pb, r0 + cm));
+    w[2] = ld<S, NT>(at<R>(src + 2 * pb, rm + c0));
+    w[3] = ld<S, NT>(at<R>(src + 3 * pb, r0 + cp));
+    w[4] = ld<S, NT>(at<R>(src + 4 * pb, rp + c0));
+    w[5] = ld<S, NT>(at<R>(src + 5 * pb, rm + cm));
+    w[6] = ld<S, NT>(at<R>(src + 6 * pb, rm + cp));
+    w[7] = ld<S, NT>(at<R>(src + 7 * pb, rp + cp));
+    w[8] = ld<S, NT>(at<R>(src + 8 * pb, rp + cm));
 }
 
 template <typename S>
-__device__ __forceinline__ void store9(typename Store<S>::raw *__restrict__ dst, int64_t P, int64_t r0, int x,
+__device__ __forceinline__ void store9(char *__restrict__ dst, uint64_t pb, uint32_t off,
                                        const typename Store<S>::wide w[9])
 {
+    using R = typename Store<S>::raw;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(Store<S>::narrow(w[i]), dst + i * P + r0 + x);
+    for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(Store<S>::narrow(w[i]), (R *)(dst + i * pb + off));
 }
 
 // One cell per lane: nine direct (possibly misaligned) loads.
@@ -125,20 +133,23 @@ __global__ void __launch_bounds__(1024) k_step_v1(StepArgs<C> a)
     using W = typename Store<S>::wide;
     constexpr bool NT = (FLAGS & 1) != 0;
     constexpr bool PIPE = (FLAGS & 2) != 0;
+    constexpr uint32_t E = sizeof(R);
     int bid = blockIdx.x;
     if (a.xcd_remap) bid = remap_xcd(bid, a.nblocks);
     const int tile_x = bid % a.tiles_x, tile_y = bid / a.tiles_x;
     const int x = tile_x * blockDim.x + threadIdx.x;
     if (x >= a.nx) return;
-    const int xm = (x == 0 ? a.nx : x) - 1;
-    const int xp = (x + 1 == a.nx) ? 0 : x + 1;
-    const R *__restrict__ src = (const R *)a.src;
-    R *__restrict__ dst = (R *)a.dst;
-    const int64_t P = a.plane;
+    const uint32_t c0 = (uint32_t)x * E;
+    const uint32_t cm = (uint32_t)((x == 0 ? a.nx : x) - 1) * E;
+    const uint32_t cp = (uint32_t)((x + 1 == a.nx) ? 0 : x + 1) * E;
+    const char *__restrict__ src = (const char *)a.src;
+    char *__restrict__ dst = (char *)a.dst;
+    const uint64_t pb = (uint64_t)a.plane * E;
+    const uint32_t rb = (uint32_t)a.pitch * E;
     auto gather = [&](int y, W w[9]) {
         const int ym = (y == 0 ? a.ny : y) - 1;
         const int yp = (y + 1 == a.ny) ? 0 : y + 1;
-        gather9<S, NT>(src, P, (int64_t)y * a.pitch, (int64_t)ym * a.pitch, (int64_t)yp * a.pitch, x, xm, xp, w);
+        gather9<S, NT>(src, pb, (uint32_t)y * rb, (uint32_t)ym * rb, (uint32_t)yp * rb, c0, cm, cp, w);
     };
     int y = tile_y * a.tile_h + threadIdx.y;
     if (y >= a.ny) return;
@@ -152,7 +163,7 @@ __global__ void __launch_bounds__(1024) k_step_v1(StepArgs<C> a)
             if (more) gather(yn, nxt);
         }
         cell_update<S, C>(w, a.r, a.scale, a.inv_scale);
-        store9<S>(dst, P, (int64_t)y * a.pitch, x, w);
+        store9<S>(dst, pb, (uint32_t)y * rb + c0, w);
         if (!more) return;
         if constexpr (PIPE) {
 #pragma unroll
@@ -176,22 +187,24 @@ __global__ void __launch_bounds__(1024) k_step_strip(StepArgs<C> a)
     using W = typename Store<S>::wide;
     constexpr bool NT = (FLAGS & 1) != 0;
     constexpr bool PIPE = (FLAGS & 2) != 0;
+    constexpr uint32_t E = sizeof(R);
     int bid = blockIdx.x;
     if (a.xcd_remap) bid = remap_xcd(bid, a.nblocks);
-    const R *__restrict__ src = (const R *)a.src;
-    R *__restrict__ dst = (R *)a.dst;
-    const int64_t P = a.plane;
+    const char *__restrict__ src = (const char *)a.src;
+    char *__restrict__ dst = (char *)a.dst;
+    const uint64_t pb = (uint64_t)a.plane * E;
+    const uint32_t rb = (uint32_t)a.pitch * E;
     const int y0 = bid * a.tile_h + threadIdx.y;
     for (int rr = 0; rr < a.rows; ++rr) {
         const int y = y0 + rr * blockDim.y;
         if (y >= a.ny) return;
         const int ym = (y == 0 ? a.ny : y) - 1;
         const int yp = (y + 1 == a.ny) ? 0 : y + 1;
-        const int64_t r0 = (int64_t)y * a.pitch, rm = (int64_t)ym * a.pitch, rp = (int64_t)yp * a.pitch;
+        const uint32_t r0 = (uint32_t)y * rb, rm = (uint32_t)ym * rb, rp = (uint32_t)yp * rb;
         auto gather = [&](int x, W w[9]) {
-            const int xm = (x == 0 ? a.nx : x) - 1;
-            const int xp = (x + 1 == a.nx) ? 0 : x + 1;
-            gather9<S, NT>(src, P, r0, rm, rp, x, xm, xp, w);
+            const uint32_t cm = (uint32_t)((x == 0 ? a.nx : x) - 1) * E;
+            const uint32_t cp = (uint32_t)((x + 1 == a.nx) ? 0 : x + 1) * E;
+            gather9<S, NT>(src, pb, r0, rm, rp, (uint32_t)x * E, cm, cp, w);
         };
         int x = threadIdx.x;
         if (x >= a.nx) continue;
@@ -205,7 +218,7 @@ __global__ void __launch_bounds__(1024) k_step_strip(StepArgs<C> a)
                 if (more) gather(xn, nxt);
             }
             cell_update<S, C>(w, a.r, a.scale, a.inv_scale);
-            store9<S>(dst, P, r0, x, w);
+            store9<S>(dst, pb, r0 + (uint32_t)x * E, w);
             if (!more) break;
             if constexpr (PIPE) {
 #pragma unroll
@@ -306,6 +319,87 @@ __global__ void __launch_bounds__(1024) k_step_vec(StepArgs<C> a)
     }
 }
 
+// VX consecutive cells per lane from overlapping aligned vector loads: a
+// population with v_x = +1 needs x0-1 .. x0+VX-2, taken from the aligned
+// vectors at x0-VX and x0; one with v_x = -1 needs x0+1 .. x0+VX, from the
+// vectors at x0 and x0+VX (both wrap periodically).  The neighbouring
+// vectors are the adjacent lanes' own vectors, so the extra loads are
+// served by the cache; there is no cross-lane exchange and no divergent
+// edge load.  Needs nx % VX == 0.
+template <typename S, typename C, int VX, int FLAGS>
+__global__ void __launch_bounds__(1024) k_step_wide(StepArgs<C> a)
+{
+    constexpr bool NT = (FLAGS & 1) != 0;
+    using R = typename Store<S>::raw;
+    using W = typename Store<S>::wide;
+    using V = typename VecOf<R, VX>::type;
+    int bid = blockIdx.x;
+    if (a.xcd_remap) bid = remap_xcd(bid, a.nblocks);
+    const int tile_x = bid % a.tiles_x, tile_y = bid / a.tiles_x;
+    const int x0 = (tile_x * (int)blockDim.x + (int)threadIdx.x) * VX;
+    if (x0 >= a.nx) return;
+    const int xl = (x0 == 0 ? a.nx : x0) - VX;           // previous vector (wrapped)
+    const int xr = (x0 + VX == a.nx) ? 0 : x0 + VX;       // next vector (wrapped)
+    const R *__restrict__ src = (const R *)a.src;
+    R *__restrict__ dst = (R *)a.dst;
+    const int64_t P = a.plane;
+    auto vload = [&](const R *p) -> V {
+        if constexpr (NT) return __builtin_nontemporal_load((const V *)p);
+        else return *(const V *)p;
+    };
+    auto el = [](const V &v, int k) -> R {
+        if constexpr (VX == 1) return v;
+        else return v[k];
+    };
+    int y = tile_y * a.tile_h + threadIdx.y;
+    for (int rr = 0; rr < a.rows; ++rr, y += blockDim.y) {
+        if (y >= a.ny) return;
+        const int ym = (y == 0 ? a.ny : y) - 1;
+        const int yp = (y + 1 == a.ny) ? 0 : y + 1;
+        const int64_t rowoff[3] = {(int64_t)y * a.pitch, (int64_t)ym * a.pitch, (int64_t)yp * a.pitch};
+        constexpr int ROW[9] = {0, 0, 1, 0, 2, 1, 1, 2, 2};
+        W w[9][VX];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const R *row = src + i * P + rowoff[ROW[i]];
+            const V cur = vload(row + x0);
+            if (VX_[i] == 0) {
+#pragma unroll
+                for (int k = 0; k < VX; ++k) w[i][k] = Store<S>::widen(el(cur, k));
+            } else if (VX_[i] == 1) {
+                const V prev = vload(row + xl);
+                w[i][0] = Store<S>::widen(el(prev, VX - 1));
+#pragma unroll
+                for (int k = 1; k < VX; ++k) w[i][k] = Store<S>::widen(el(cur, k - 1));
+            } else {
+                const V next = vload(row + xr);
+#pragma unroll
+                for (int k = 0; k < VX - 1; ++k) w[i][k] = Store<S>::widen(el(cur, k + 1));
+                w[i][VX - 1] = Store<S>::widen(el(next, 0));
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < VX; ++k) {
+            W c[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) c[i] = w[i][k];
+            cell_update<S, C>(c, a.r, a.scale, a.inv_scale);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) w[i][k] = c[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            V out;
+#pragma unroll
+            for (int k = 0; k < VX; ++k) {
+                if constexpr (VX == 1) out = Store<S>::narrow(w[i][k]);
+                else out[k] = Store<S>::narrow(w[i][k]);
+            }
+            __builtin_nontemporal_store(out, (V *)(dst + i * P + rowoff[0] + x0));
+        }
+    }
+}
+
 // ---- batched step over a pool of lattices ----------------------------------------
 //
 // One launch advances every active member of one storage class by one step.
@@ -339,10 +433,12 @@ __global__ void __launch_bounds__(1024) k_pool_step(const PoolHeader *hdr, const
         const int64_t done = m->t_done;
         if (done + k >= m->t_target) continue;
         const int par = (int)((m->cur0 + done + k) & 1);
-        const R *__restrict__ src = (const R *)m->buf[par];
-        R *__restrict__ dst = (R *)m->buf[par ^ 1];
-        const int nx = m->nx, ny = m->ny, pitch = m->pitch;
-        const int64_t P = m->plane;
+        const char *__restrict__ src = (const char *)m->buf[par];
+        char *__restrict__ dst = (char *)m->buf[par ^ 1];
+        const int nx = m->nx, ny = m->ny;
+        constexpr uint32_t E = sizeof(R);
+        const uint64_t pb = (uint64_t)m->plane * E;
+        const uint32_t rb = (uint32_t)m->pitch * E;
         const Relax<C> r = member_relax<C>(m);
         const float scale = m->scale, inv_scale = m->inv_scale;
         const int ncols = tile.ncols;
@@ -351,15 +447,15 @@ __global__ void __launch_bounds__(1024) k_pool_step(const PoolHeader *hdr, const
             const int dy = c / ncols;
             const int x = tile.x0 + (c - dy * ncols);
             const int y = tile.y0 + dy;
-            const int xm = (x == 0 ? nx : x) - 1;
-            const int xp = (x + 1 == nx) ? 0 : x + 1;
+            const uint32_t cm = (uint32_t)((x == 0 ? nx : x) - 1) * E;
+            const uint32_t cp = (uint32_t)((x + 1 == nx) ? 0 : x + 1) * E;
             const int ym = (y == 0 ? ny : y) - 1;
             const int yp = (y + 1 == ny) ? 0 : y + 1;
-            const int64_t r0 = (int64_t)y * pitch;
+            const uint32_t r0 = (uint32_t)y * rb;
             W w[9];
-            gather9<S, false>(src, P, r0, (int64_t)ym * pitch, (int64_t)yp * pitch, x, xm, xp, w);
+            gather9<S, false>(src, pb, r0, (uint32_t)ym * rb, (uint32_t)yp * rb, (uint32_t)x * E, cm, cp, w);
             cell_update<S, C>(w, r, scale, inv_scale);
-            store9<S>(dst, P, r0, x, w);
+            store9<S>(dst, pb, r0 + (uint32_t)x * E, w);
         }
     }
 }
@@ -656,7 +752,7 @@ hipError_t launch_step_typed(const View &v, const void *src, void *dst, const lb
     a.nx = v.nx;
     a.ny = v.ny;
     a.pitch = v.pitch;
-    const int vx = cfg.variant <= 3 ? 1 << cfg.variant : 1;
+    const int vx = cfg.variant <= 3 ? 1 << cfg.variant : (cfg.variant >= 5 ? 1 << (cfg.variant - 4) : 1);
     const int tile_w = cfg.block_x * vx;
     a.tiles_x = cfg.variant == 4 ? 1 : (v.nx + tile_w - 1) / tile_w;
     a.tile_h = cfg.block_y * cfg.rows;
@@ -685,6 +781,12 @@ hipError_t launch_step_typed(const View &v, const void *src, void *dst, const lb
     case 17: hipLaunchKernelGGL((k_step_strip<S, C, 1>), grid, block, 0, st, a); break;
     case 18: hipLaunchKernelGGL((k_step_strip<S, C, 2>), grid, block, 0, st, a); break;
     case 19: hipLaunchKernelGGL((k_step_strip<S, C, 3>), grid, block, 0, st, a); break;
+    case 20: hipLaunchKernelGGL((k_step_wide<S, C, 2, 0>), grid, block, 0, st, a); break;
+    case 21: hipLaunchKernelGGL((k_step_wide<S, C, 2, 1>), grid, block, 0, st, a); break;
+    case 24: hipLaunchKernelGGL((k_step_wide<S, C, 4, 0>), grid, block, 0, st, a); break;
+    case 25: hipLaunchKernelGGL((k_step_wide<S, C, 4, 1>), grid, block, 0, st, a); break;
+    case 28: hipLaunchKernelGGL((k_step_wide<S, C, 8, 0>), grid, block, 0, st, a); break;
+    case 29: hipLaunchKernelGGL((k_step_wide<S, C, 8, 1>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -783,7 +885,7 @@ size_t storage_bytes(int32_t storage)
 
 bool step_shape_supported(const View &v, const lbm_launch &cfg)
 {
-    if (cfg.variant < 0 || cfg.variant > 4) return false;
+    if (cfg.variant < 0 || cfg.variant > 7) return false;
     if (cfg.block_x < 1 || cfg.block_y < 1 || cfg.rows < 1 || cfg.rows > 64) return false;
     if (cfg.block_x * cfg.block_y > 1024 || cfg.block_x * cfg.block_y < 64) return false;
     if (cfg.block_x % 64 != 0 && cfg.block_x * cfg.block_y % 64 != 0) return false;
@@ -794,6 +896,7 @@ bool step_shape_supported(const View &v, const lbm_launch &cfg)
         const int vx = 1 << cfg.variant;
         if (cfg.block_x % 64 != 0 || v.nx % vx != 0) return false;
     }
+    if (cfg.variant >= 5 && v.nx % (1 << (cfg.variant - 4)) != 0) return false;
     return true;
 }
 

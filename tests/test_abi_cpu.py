@@ -66,7 +66,8 @@ def test_workspace_bytes_formula(storage, es):
     dict(nx=0), dict(ny=-3), dict(s=(0.0, 1.5, 1.5, 1.5)), dict(s=(1.5, 2.01, 1.5, 1.5)),
     dict(s=(1.5, 1.5, float("nan"), 1.5)), dict(rho0=0.0), dict(rho0=float("inf")),
     dict(u0x=float("nan")), dict(storage=7), dict(compute=3), dict(storage=1, compute=0),
-    dict(storage=2, compute=0), dict(scale_exp=99), dict(nx=70000, ny=70000)])
+    dict(storage=2, compute=0), dict(scale_exp=99), dict(nx=70000, ny=70000),
+    dict(nx=32768, ny=16384, storage=0, compute=0)])     # one FP64 plane of 4 GiB
 def test_invalid_descriptors_are_rejected(bad):
     d = desc(**bad)
     assert _lib.lbm_workspace_bytes(d) == 0
@@ -74,6 +75,11 @@ def test_invalid_descriptors_are_rejected(bad):
         _lib.lbm_create(d, 256, 1 << 40, 0)
     assert e.value.status == _lib.LBM_E_INVAL
     assert _lib.lbm_last_error() != ""
+
+
+def test_largest_planes_are_accepted():
+    # one FP32 plane just below 4 GiB (32768 x 32767 cells)
+    assert _lib.lbm_workspace_bytes(desc(nx=32768, ny=32767)) > 2 * 9 * 32768 * 32767 * 4
 
 
 def test_rate_two_is_accepted():

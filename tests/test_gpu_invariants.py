@@ -67,7 +67,7 @@ def test_checkpoint_resume_is_bitwise(storage):
     assert torch.equal(a.populations(), c.populations())
 
 
-@pytest.mark.parametrize("storage", ["f32", "f64"])
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16", "bf16"])
 def test_all_launch_shapes_give_identical_results(storage):
     nx, ny = 256, 72
     rho, ux, uy = fields(nx, ny, 3, (0.02, 0.01))
@@ -81,7 +81,10 @@ def test_all_launch_shapes_give_identical_results(storage):
                    dict(variant=0, block_x=64, block_y=2, rows=4, xcd_remap=0, flags=3),
                    dict(variant=2, block_x=64, block_y=2, rows=1, xcd_remap=0, flags=1),
                    dict(variant=4, block_x=128, block_y=4, rows=2, xcd_remap=0, flags=2),
-                   dict(variant=4, block_x=1024, block_y=1, rows=1, xcd_remap=1, flags=3)]:
+                   dict(variant=4, block_x=1024, block_y=1, rows=1, xcd_remap=1, flags=3),
+                   dict(variant=5, block_x=256, block_y=1, rows=2, xcd_remap=0, flags=1),
+                   dict(variant=6, block_x=64, block_y=4, rows=1, xcd_remap=1, flags=0),
+                   dict(variant=7, block_x=16, block_y=4, rows=3, xcd_remap=0, flags=1)]:
         lat = lattice(nx, ny, s, storage, u0=(0.02, 0.01))
         lat.set_launch(**launch)
         f = lat.init(rho, ux, uy).step(25).populations()

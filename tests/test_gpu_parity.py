@@ -58,7 +58,10 @@ VARIANTS = [dict(variant=0, block_x=64, block_y=4, rows=1, xcd_remap=1),
             dict(variant=3, block_x=128, block_y=1, rows=4, xcd_remap=0),
             dict(variant=0, block_x=128, block_y=2, rows=3, xcd_remap=0, flags=3),
             dict(variant=4, block_x=64, block_y=2, rows=2, xcd_remap=0, flags=2),
-            dict(variant=4, block_x=256, block_y=1, rows=1, xcd_remap=1, flags=1)]
+            dict(variant=4, block_x=256, block_y=1, rows=1, xcd_remap=1, flags=1),
+            dict(variant=5, block_x=64, block_y=4, rows=1, xcd_remap=0, flags=0),
+            dict(variant=6, block_x=128, block_y=2, rows=2, xcd_remap=1, flags=1),
+            dict(variant=7, block_x=32, block_y=2, rows=1, xcd_remap=0, flags=0)]
 
 
 @pytest.mark.parametrize("launch", VARIANTS)
