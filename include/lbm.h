@@ -200,6 +200,13 @@ LBM_API lbm_status lbm_read_populations(lbm_lattice *lat, double *dev_f);
  * t is left unchanged.  Enqueued. */
 LBM_API lbm_status lbm_write_populations(lbm_lattice *lat, const double *dev_f);
 
+/* Imposes the equilibrium f(x, y, t) = f^eq(rho, rho u) on one node of the
+ * current (pre-collision) state: the point source of Sec. 5.1 prescribes the
+ * density of a node every step with zero velocity.  Call it after each
+ * lbm_step.  rho > 0, all finite, 0 <= x < nx, 0 <= y < ny.  Enqueued. */
+LBM_API lbm_status lbm_set_node_equilibrium(lbm_lattice *lat, int32_t x, int32_t y, double rho, double ux,
+                                            double uy);
+
 /* Bytes of the raw state (the current buffer in its storage type). */
 LBM_API size_t lbm_state_bytes(const lbm_lattice *lat);
 /* Bitwise checkpoint of the raw state into / from a device buffer of

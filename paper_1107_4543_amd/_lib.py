@@ -78,6 +78,8 @@ SIGNATURES = {
     "lbm_project": (_st, [_vp, ctypes.c_int32, ctypes.c_int32, _vp]),
     "lbm_read_populations": (_st, [_vp, _vp]),
     "lbm_write_populations": (_st, [_vp, _vp]),
+    "lbm_set_node_equilibrium": (_st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double]),
     "lbm_state_bytes": (ctypes.c_size_t, [_vp]),
     "lbm_save_state": (_st, [_vp, _vp]),
     "lbm_load_state": (_st, [_vp, _vp, ctypes.c_int64]),
@@ -196,6 +198,11 @@ def lbm_read_populations(h, dev_f):
 
 def lbm_write_populations(h, dev_f):
     check(load().lbm_write_populations(h, _vp(dev_f)), "lbm_write_populations")
+
+
+def lbm_set_node_equilibrium(h, x, y, rho, ux, uy):
+    check(load().lbm_set_node_equilibrium(h, int(x), int(y), float(rho), float(ux), float(uy)),
+          "lbm_set_node_equilibrium")
 
 
 def lbm_state_bytes(h):

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_kernels.hip", "lbm_api.hip", "lbm_pool.hip"]
+SOURCES = ["lbm_kernels.hip", "lbm_api.hip", "lbm_pool.hip", "lbm_source.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

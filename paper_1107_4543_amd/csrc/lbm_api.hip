@@ -376,6 +376,17 @@ lbm_status lbm_write_populations(lbm_lattice *lat, const double *dev_f)
     return LBM_OK;
 }
 
+lbm_status lbm_set_node_equilibrium(lbm_lattice *lat, int32_t x, int32_t y, double rho, double ux, double uy)
+{
+    if (!lat) return fail(LBM_E_INVAL, "lattice is NULL");
+    if (!lat->initialized) return fail(LBM_E_STATE, "set node before init");
+    if (lat->pool) return busy(lat);
+    if (x < 0 || y < 0 || x >= lat->v.nx || y >= lat->v.ny) return fail(LBM_E_INVAL, "node (%d, %d) outside the lattice", x, y);
+    if (!isfinite(rho) || rho <= 0.0 || !isfinite(ux) || !isfinite(uy)) return fail(LBM_E_INVAL, "rho must be finite and > 0, u finite");
+    hipError_t e = lbm::launch_set_node(lat->v, lat->buf[lat->cur], x, y, rho, ux, uy, lat->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "set node");
+}
+
 size_t lbm_state_bytes(const lbm_lattice *lat) { return lat ? lat->state_bytes : 0; }
 
 lbm_status lbm_save_state(lbm_lattice *lat, void *dev_dst)

@@ -46,6 +46,10 @@ hipError_t launch_diagnostics(const View &v, const void *src, double *partials, 
 hipError_t launch_project(const View &v, const void *src, int32_t mx, int32_t my,
                           double *partials, double *out, hipStream_t st);
 
+// Sets the pre-collision populations of cell (x, y) to f^eq(rho, rho u).
+hipError_t launch_set_node(const View &v, void *dst, int32_t x, int32_t y, double rho, double ux, double uy,
+                           hipStream_t st);
+
 // ---- batched stepping (pool) --------------------------------------------------
 
 // Storage/compute class of a lattice: storage * 2 + compute (8 values).

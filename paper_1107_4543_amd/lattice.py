@@ -124,6 +124,11 @@ class Lattice:
             _lib.lbm_write_populations(self._h, f.data_ptr())
         return self
 
+    def set_node_equilibrium(self, x, y, rho, ux=0.0, uy=0.0):
+        """Imposes f(x, y) = f^eq(rho, rho u) on one node (point source)."""
+        _lib.lbm_set_node_equilibrium(self._h, x, y, rho, ux, uy)
+        return self
+
     def save_state(self):
         with torch.cuda.stream(self.stream):
             buf = torch.empty(_lib.lbm_state_bytes(self._h), dtype=torch.uint8, device=self.device)

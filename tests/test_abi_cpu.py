@@ -105,7 +105,8 @@ def test_create_checks_workspace_and_call_order_without_touching_the_device():
         assert _lib.lbm_time(h) == 0
         for fn, args in [(_lib.lbm_step, (1,)), (_lib.lbm_read_moments, (8, 8, 8)),
                          (_lib.lbm_read_populations, (8,)), (_lib.lbm_save_state, (8,)),
-                         (_lib.lbm_project, (1, 0, 8)), (_lib.lbm_tune, (3,))]:
+                         (_lib.lbm_project, (1, 0, 8)), (_lib.lbm_tune, (3,)),
+                         (_lib.lbm_set_node_equilibrium, (1, 1, 1.0, 0.0, 0.0))]:
             with pytest.raises(_lib.LbmError) as e:
                 fn(h, *args)
             assert e.value.status == _lib.LBM_E_STATE, fn.__name__

@@ -1,0 +1,84 @@
+"""The acoustic point source of Sec. 5.1: a 101 x 101 periodic lattice whose
+centre node is held at rho = rho0 + rho_s sin(2 pi t / T), u = 0, every step
+(rho_s = 0.01; T is not given in the paper, 20 steps are used), for the
+Table 4 group A rates (optimised MRT), the original MRT with the same shear
+viscosity, and BGK with the same viscosity (equal rates, Eq. eq_BGK_LBM_R).
+Up to t = 86 = floor(50 / c_s) the waves stay inside the domain.
+
+Checks: FP64 parity with the oracle (the oracle imposes the same node
+equilibrium after each of its own steps); exact eight-fold symmetry about
+the source; and exact causality (cells farther than t - 1 from the source in
+the max norm are untouched: the source is first imposed after step 1 and
+populations move at most one cell per step)."""
+import math
+
+import numpy as np
+import pytest
+
+import lbm_inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+N, C, RHO_S, PERIOD = 101, 50, 0.01, 20.0
+T4A = lbm_inputs.PRESETS["T4A"]
+SETS = {"optimised": [T4A["s_e"], T4A["s_eps"], T4A["s_q"], T4A["s_nu"]],
+        "original": [1.64, 1.54, 1.9, T4A["s_nu"]],
+        "bgk": [T4A["s_nu"]] * 4}
+
+
+def source_rho(t):
+    return 1.0 + RHO_S * math.sin(2 * math.pi * t / PERIOD)
+
+
+def run_gpu(s, steps, storage="f64"):
+    from paper_1107_4543_amd import Lattice
+    lat = Lattice(N, N, *s, storage=storage, device="cuda:0")
+    lat.init(np.ones((N, N)), np.zeros((N, N)), np.zeros((N, N)))
+    for t in range(1, steps + 1):
+        lat.step(1).set_node_equilibrium(C, C, source_rho(t))
+    return lat.populations().cpu().numpy()
+
+
+def run_oracle(s, steps):
+    f = oracle.init(np.ones((N, N)), np.zeros((N, N)), np.zeros((N, N)))
+    for t in range(1, steps + 1):
+        f = oracle.run(f, s, 1)
+        f[:, C, C] = oracle.init(np.full((1, 1), source_rho(t)), np.zeros((1, 1)), np.zeros((1, 1)))[:, 0, 0]
+    return f
+
+
+@pytest.mark.parametrize("name", list(SETS))
+def test_point_source_parity_symmetry_and_causality(name):
+    s = SETS[name]
+    steps = 40
+    f = run_gpu(s, steps)
+    ref = run_oracle(s, steps)
+    assert np.max(np.abs(f - ref)) <= 1e-12 * np.max(np.abs(ref))
+    rho = f.sum(axis=0)
+    assert np.max(np.abs(rho - rho.T)) < 1e-14
+    assert np.max(np.abs(rho - rho[::-1, :])) < 1e-14 and np.max(np.abs(rho - rho[:, ::-1])) < 1e-14
+    d = np.maximum(np.abs(np.arange(N) - C)[None, :], np.abs(np.arange(N) - C)[:, None])
+    base = run_gpu(s, 0)[:, 0, 0]            # the library's own uniform state
+    # the source is first imposed after step 1 and leaves its node during
+    # step 2: after `steps` steps it has reached max-norm distance steps - 1
+    far = d > steps - 1
+    assert np.array_equal(f[:, far], np.broadcast_to(base[:, None], f[:, far].shape))
+    # the signal has arrived ten rings inside the light cone (the outermost
+    # rings carry almost nothing with the optimised rates, which suppress the
+    # fast spurious components)
+    assert np.any(f[:, d == steps - 10] != base[:, None])
+
+
+def test_point_source_waves_until_the_containment_time():
+    # t = 86 for all three schemes; report the axis/diagonal amplitude ratio
+    # of the outermost crest (isotropy), and check FP32 against FP64.
+    out = {}
+    for name, s in SETS.items():
+        rho = run_gpu(s, 86).sum(axis=0) - 1.0
+        axis = np.max(np.abs(rho[C, C + 30:C + 50]))
+        diag = np.max(np.abs(np.array([rho[C + k, C + k] for k in range(21, 36)])))
+        out[name] = axis / diag
+        r32 = run_gpu(s, 86, "f32").sum(axis=0) - 1.0
+        assert np.max(np.abs(r32 - rho)) < 1e-5 * RHO_S
+    print("axis/diagonal crest ratio at t = 86:", {k: round(v, 4) for k, v in out.items()})
