@@ -82,3 +82,55 @@ def test_point_source_waves_until_the_containment_time():
         r32 = run_gpu(s, 86, "f32").sum(axis=0) - 1.0
         assert np.max(np.abs(r32 - rho)) < 1e-5 * RHO_S
     print("axis/diagonal crest ratio at t = 86:", {k: round(v, 4) for k, v in out.items()})
+
+
+def _acoustic_wavelength(s, omega):
+    """Wavelength along the x axis at which the acoustic eigenvalue of G(k)
+    (Sec. 4.1) turns by omega per step."""
+    from scipy.optimize import brentq
+    from oracle import linear
+
+    def phase(k):
+        w = -np.angle(linear.eigen(k, 0.0, *s)[0])
+        return w[np.argmin(np.abs(w - linear.CS * k))] - omega
+    return 2 * math.pi / brentq(phase, 0.3, 0.8)
+
+
+def _crests(p):
+    """Sub-cell positions (parabola through the three nodes) of the local
+    maxima of a profile to the right of the source."""
+    out = []
+    for x in range(C + 2, N - 1):
+        if p[x] > p[x - 1] and p[x] >= p[x + 1]:
+            out.append(x + 0.5 * (p[x - 1] - p[x + 1]) / (p[x - 1] - 2 * p[x] + p[x + 1]))
+    return np.array(out)
+
+
+def test_point_source_profiles_at_y51():
+    # Density profiles along the row through the source (y = 51 counting from
+    # 1) at t = 80 and t = 100.  The optimised rates give one crest per
+    # wavelength, spaced by the linear-theory wavelength at the source
+    # frequency; BGK at the same viscosity adds grid-scale spurious
+    # oscillations (many more local maxima), the original MRT a few.
+    lam = _acoustic_wavelength(SETS["optimised"], 2 * math.pi / PERIOD)
+    counts = {}
+    for name, s in SETS.items():
+        from paper_1107_4543_amd import Lattice
+        lat = Lattice(N, N, *s, storage="f64", device="cuda:0")
+        lat.init(np.ones((N, N)), np.zeros((N, N)), np.zeros((N, N)))
+        for t in range(1, 101):
+            lat.step(1).set_node_equilibrium(C, C, source_rho(t))
+            if t in (80, 100):
+                p = lat.moments()[0].cpu().numpy()[C, :] - 1.0
+                print(name, "t =", t, "rho - 1 along y = 51:", " ".join("%.2e" % v for v in p[C:]))
+                cr = _crests(p)
+                counts[(name, t)] = len(cr)
+                if name == "optimised":
+                    spacing = np.diff(cr)[:-1]          # the last crest is the front
+                    print("crest spacing", np.round(spacing, 3), "linear theory", round(lam, 3))
+                    assert len(spacing) >= 2
+                    assert np.all(np.abs(spacing - lam) < 0.02 * lam)
+    for t in (80, 100):
+        assert counts[("bgk", t)] >= 2 * counts[("optimised", t)]
+        assert counts[("optimised", t)] < counts[("original", t)] <= counts[("bgk", t)]
+    print("local maxima to the right of the source:", counts)
