@@ -11,6 +11,7 @@ no code with the GPU path.
   the paper's printed linear collision matrix Psi (Sec. 2.3, Sec. 4.1).
 * ``oracle.exact_pulse`` evaluates the exact acoustic pulse solution
   (Sec. 5.2).
+* ``oracle.storage`` is the rounding twin for 16-bit population storage.
 """
 import ctypes
 import os
