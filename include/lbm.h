@@ -110,14 +110,22 @@ typedef struct lbm_lattice lbm_lattice;
  *             5, 6, 7 = 2, 4, 8 consecutive cells per lane, x-shifted values
  *             taken from overlapping aligned vector loads (needs
  *             nx % 2^(variant-4) == 0)
+ *             8, 9, 10 = T = 2, 3, 4 steps per launch (temporal blocking in
+ *             registers): each wave of 64 lanes owns a strip of 64 - 2(T-1)
+ *             columns and a segment of `rows` rows; block_x must be 64,
+ *             block_y (waves per workgroup) 1..4, rows 1..4096.  lbm_step(n)
+ *             then makes n / T such launches and n % T one-step launches
+ *             (with the one-step shape last set or found by lbm_tune).
  *   block_x   lanes along x per workgroup, block_y rows per workgroup pass;
  *             64 <= block_x * block_y <= 1024
  *   rows      rows each lane processes, 1..64 (tile height = block_y * rows)
  *   xcd_remap 1 = renumber workgroups so that neighbouring tiles run on the
  *             same XCD (shared L2), 0 = hardware order
- *   flags     bit 0: non-temporal loads; bit 1: issue the next row's (variant
- *             0) or next chunk's (variant 4) loads before colliding the current
- *             cells (variants 0 and 4 only).
+ *   flags     bit 0: non-temporal loads; bit 1: issue the next row's (variants
+ *             0, 8, 9, 10) or next chunk's (variant 4) loads before colliding
+ *             the current cells (variants 0, 4, 8, 9, 10 only); bit 2
+ *             (variants 8, 9, 10 only): move values between neighbouring
+ *             lanes with DPP whole-wave shifts instead of LDS shuffles.
  * Every shape produces bit-identical results. */
 typedef struct lbm_launch {
     int32_t variant;
@@ -221,12 +229,17 @@ LBM_API int64_t lbm_time(const lbm_lattice *lat);
 LBM_API lbm_status lbm_get_launch(const lbm_lattice *lat, lbm_launch *out);
 /* LBM_E_INVAL if the shape is not supported for this lattice. */
 LBM_API lbm_status lbm_set_launch(lbm_lattice *lat, const lbm_launch *cfg);
-/* Times every supported launch shape on this lattice (reps launches each,
- * the state is left unchanged) and selects the fastest.  best/best_us may
- * be NULL.  Syncs. */
+/* Times the supported launch shapes on this lattice (reps launches each,
+ * the state is left unchanged) and selects the one with the least time per
+ * step; the fastest one-step shape is kept for left-over steps.  best_us
+ * receives microseconds per step.  best/best_us may be NULL.  Syncs. */
 LBM_API lbm_status lbm_tune(lbm_lattice *lat, int32_t reps, lbm_launch *best, double *best_us);
-/* Times n launches of the current shape (state unchanged; syncs). */
+/* Times n launches of the current shape (state unchanged; syncs); avg_us is
+ * per launch, which covers lbm_steps_per_launch steps. */
 LBM_API lbm_status lbm_time_launches(lbm_lattice *lat, int32_t n, double *avg_us);
+/* Steps one launch of this shape advances (1, or T for variants 8-10);
+ * 0 if cfg is NULL.  Does not validate the shape. */
+LBM_API int32_t lbm_steps_per_launch(const lbm_launch *cfg);
 
 /* ---- pools: many lattices advanced together ------------------------------
  *

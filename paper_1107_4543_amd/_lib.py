@@ -88,6 +88,7 @@ SIGNATURES = {
     "lbm_set_launch": (_st, [_vp, ctypes.POINTER(lbm_launch)]),
     "lbm_tune": (_st, [_vp, ctypes.c_int32, ctypes.POINTER(lbm_launch), _dp]),
     "lbm_time_launches": (_st, [_vp, ctypes.c_int32, _dp]),
+    "lbm_steps_per_launch": (ctypes.c_int32, [ctypes.c_void_p]),
     "lbm_pool_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "lbm_pool_create": (_st, [_vp, ctypes.c_size_t, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_vp)]),
     "lbm_pool_destroy": (_st, [_vp]),
@@ -242,6 +243,10 @@ def lbm_time_launches(h, n):
     us = ctypes.c_double()
     check(load().lbm_time_launches(h, int(n), ctypes.byref(us)), "lbm_time_launches")
     return us.value
+
+
+def lbm_steps_per_launch(cfg):
+    return int(load().lbm_steps_per_launch(ctypes.byref(cfg)))
 
 
 # ---- pools ----------------------------------------------------------------------

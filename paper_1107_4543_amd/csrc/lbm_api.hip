@@ -136,6 +136,27 @@ std::vector<lbm_launch> variant_candidates(const View &v, const lbm_launch &best
     return out;
 }
 
+// Tuner stage 3: shapes that advance several steps per launch.
+std::vector<lbm_launch> multi_candidates(const View &v)
+{
+    std::vector<lbm_launch> out;
+    for (int var = 8; var <= 10; ++var)
+        for (int by : {1, 2, 4})
+            for (int rows : {32, 64, 128, 256})
+                for (int flags : {0, 2, 4, 6})
+                    for (int remap = 0; remap < 2; ++remap) {
+                        lbm_launch c{};
+                        c.variant = var;
+                        c.block_x = 64;
+                        c.block_y = by;
+                        c.rows = rows;
+                        c.xcd_remap = remap;
+                        c.flags = flags;
+                        if (rows <= 2 * v.ny && lbm::step_shape_supported(v, c)) out.push_back(c);
+                    }
+    return out;
+}
+
 lbm_status time_shape(lbm_lattice *L, const lbm_launch &c, int reps, double *us)
 {
     hipEvent_t e0, e1;
@@ -245,6 +266,7 @@ lbm_status lbm_create(const lbm_desc *desc, void *dev_ws, size_t ws_bytes, void 
     L->result = L->partials + (size_t)lbm::kRedBlocks * lbm::kRedWidth;
     L->stream = (hipStream_t)stream;
     L->launch = default_launch(v);
+    L->single = L->launch;
     *out = L;
     return LBM_OK;
 }
@@ -310,11 +332,17 @@ lbm_status lbm_step(lbm_lattice *lat, int64_t n)
     if (n < 0) return fail(LBM_E_INVAL, "n must be >= 0");
     if (!lat->initialized) return fail(LBM_E_STATE, "lbm_step before lbm_init_equilibrium");
     if (lat->pool) return busy(lat);
-    for (int64_t k = 0; k < n; ++k) {
-        hipError_t e = lbm::launch_step(lat->v, lat->buf[lat->cur], lat->buf[lat->cur ^ 1], lat->launch, lat->stream);
+    // a shape that advances T steps per launch takes n / T launches; the
+    // remaining n % T steps use the one-step shape
+    const int T = lbm::steps_per_launch(lat->launch);
+    for (int64_t k = 0; k < n;) {
+        const bool multi = n - k >= T;
+        const lbm_launch &c = multi ? lat->launch : lat->single;
+        hipError_t e = lbm::launch_step(lat->v, lat->buf[lat->cur], lat->buf[lat->cur ^ 1], c, lat->stream);
         if (e != hipSuccess) return hip_fail(e, "step launch");
         lat->cur ^= 1;
-        lat->t += 1;
+        lat->t += multi ? T : 1;
+        k += multi ? T : 1;
     }
     return LBM_OK;
 }
@@ -429,8 +457,11 @@ lbm_status lbm_set_launch(lbm_lattice *lat, const lbm_launch *cfg)
         return fail(LBM_E_INVAL, "launch shape (variant %d, %dx%d, rows %d) not supported for nx=%d", cfg->variant,
                     cfg->block_x, cfg->block_y, cfg->rows, lat->v.nx);
     lat->launch = *cfg;
+    if (lbm::steps_per_launch(*cfg) == 1) lat->single = *cfg;
     return LBM_OK;
 }
+
+int32_t lbm_steps_per_launch(const lbm_launch *cfg) { return cfg ? lbm::steps_per_launch(*cfg) : 0; }
 
 lbm_status lbm_time_launches(lbm_lattice *lat, int32_t n, double *avg_us)
 {
@@ -449,10 +480,16 @@ lbm_status lbm_tune(lbm_lattice *lat, int32_t reps, lbm_launch *best, double *be
         double us;
         lbm_launch c;
     };
+    // shapes are ranked by time per step
+    auto per_step = [&](const lbm_launch &c, int r, double *us) -> lbm_status {
+        lbm_status st = time_shape(lat, c, r, us);
+        if (st == LBM_OK) *us /= lbm::steps_per_launch(c);
+        return st;
+    };
     auto sweep = [&](const std::vector<lbm_launch> &cands, int r, std::vector<Timed> &out) -> lbm_status {
         for (const lbm_launch &c : cands) {
             double us;
-            lbm_status st = time_shape(lat, c, r, &us);
+            lbm_status st = per_step(c, r, &us);
             if (st != LBM_OK) return st;
             out.push_back({us, c});
         }
@@ -477,6 +514,10 @@ lbm_status lbm_tune(lbm_lattice *lat, int32_t reps, lbm_launch *best, double *be
         }
     std::vector<Timed> s2 = s1;
     if ((st = sweep(c2, reps, s2)) != LBM_OK) return st;
+    // the best one-step shape also serves the steps a multi-step shape leaves over
+    const lbm_launch best_single = s2.front().c;
+    // stage 3: several steps per launch
+    if ((st = sweep(multi_candidates(lat->v), reps, s2)) != LBM_OK) return st;
     // final: re-time the six best with more launches, twice, keep the minimum
     std::vector<Timed> fin;
     for (size_t k = 0; k < s2.size() && fin.size() < 6; ++k) {
@@ -484,12 +525,13 @@ lbm_status lbm_tune(lbm_lattice *lat, int32_t reps, lbm_launch *best, double *be
         for (const Timed &d : fin) dup = dup || same(s2[k].c, d.c);
         if (dup) continue;
         double a, b;
-        if ((st = time_shape(lat, s2[k].c, 4 * reps, &a)) != LBM_OK) return st;
-        if ((st = time_shape(lat, s2[k].c, 4 * reps, &b)) != LBM_OK) return st;
+        if ((st = per_step(s2[k].c, 4 * reps, &a)) != LBM_OK) return st;
+        if ((st = per_step(s2[k].c, 4 * reps, &b)) != LBM_OK) return st;
         fin.push_back({std::min(a, b), s2[k].c});
     }
     std::sort(fin.begin(), fin.end(), [](const Timed &a, const Timed &b) { return a.us < b.us; });
     lat->launch = fin.front().c;
+    lat->single = best_single;
     if (best) *best = fin.front().c;
     if (best_us) *best_us = fin.front().us;
     return LBM_OK;

@@ -28,6 +28,8 @@ constexpr size_t kScratchBytes = (size_t)kRedBlocks * kRedWidth * sizeof(double)
 
 size_t storage_bytes(int32_t storage);
 bool step_shape_supported(const View &v, const lbm_launch &cfg);
+// Steps one launch of this shape advances (several-steps-per-pass variants).
+int steps_per_launch(const lbm_launch &cfg);
 
 hipError_t launch_step(const View &v, const void *src, void *dst, const lbm_launch &cfg,
                        hipStream_t st);
@@ -114,5 +116,6 @@ struct lbm_lattice {
     int64_t t = 0;
     bool initialized = false;
     lbm_launch launch{};
+    lbm_launch single{};       // one-step shape for the steps a multi-step shape leaves over
     lbm_pool *pool = nullptr;  // non-NULL while a pool advances this lattice
 };

@@ -45,6 +45,7 @@ struct StepArgs {
     void *dst;
     int32_t nx, ny, pitch, tiles_x;
     int32_t tile_h, rows, nblocks, xcd_remap;
+    int32_t nwaves, pad_;
     int64_t plane;
     Relax<C> r;
     float scale, inv_scale;
@@ -396,6 +397,159 @@ __global__ void __launch_bounds__(1024) k_step_wide(StepArgs<C> a)
                 else out[k] = Store<S>::narrow(w[i][k]);
             }
             __builtin_nontemporal_store(out, (V *)(dst + i * P + rowoff[0] + x0));
+        }
+    }
+}
+
+// ---- several steps per pass (temporal blocking in registers) ---------------
+//
+// One wave owns a strip of 64 consecutive columns and walks a segment of
+// rows.  Stage 0 gathers the nine pulled values of its row from HBM and
+// collides them; stage p (p = 1 .. T-1) collides row r - p from the outputs
+// of stage p-1, which it keeps in registers: populations with v_y = +1 come
+// from the row above (kept from two iterations back), v_y = 0 from the same
+// row, v_y = -1 from the row just produced, and the one-column x-shift is a
+// cross-lane shuffle.  Only stage T-1 writes to HBM, so one pass reads and
+// writes every population once for T steps.  Each stage loses one column at
+// each wave edge (its shuffles reach outside the wave there), so a wave
+// produces the 64 - 2(T-1) middle columns; the segment is started 2(T-1)
+// rows early so that every stage has its rows above.  Intermediate stages
+// round their outputs to the storage type exactly as a store and reload
+// would, so T steps in one pass are bit-identical to T single steps.
+
+// Whole-wave shifts by one lane with DPP (wave_shr:1 / wave_shl:1 move a
+// register between neighbouring lanes inside the VALU, without the LDS
+// crossbar that a general shuffle uses).  The edge lane that has no source
+// keeps its own value; the kernel never uses that lane's result.
+constexpr int kDppWaveShl1 = 0x130;   // lane i receives lane i + 1
+constexpr int kDppWaveShr1 = 0x138;   // lane i receives lane i - 1
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_shift(float v)
+{
+    const int b = __float_as_int(v);
+    return __int_as_float(__builtin_amdgcn_update_dpp(b, b, CTRL, 0xf, 0xf, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift(double v)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
+    const uint32_t nlo = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+    const uint32_t nhi = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((uint64_t)nhi << 32) | nlo));
+}
+
+// value of the lane to the left (column x - 1) / to the right (column x + 1)
+template <bool DPP, typename V>
+__device__ __forceinline__ V from_left(V v)
+{
+    if constexpr (DPP) return dpp_shift<kDppWaveShr1>(v);
+    else return __shfl_up(v, 1, 64);
+}
+
+template <bool DPP, typename V>
+__device__ __forceinline__ V from_right(V v)
+{
+    if constexpr (DPP) return dpp_shift<kDppWaveShl1>(v);
+    else return __shfl_down(v, 1, 64);
+}
+
+template <typename S>
+__device__ __forceinline__ typename Store<S>::wide round_trip(typename Store<S>::wide v)
+{
+    return Store<S>::widen(Store<S>::narrow(v));
+}
+
+__device__ __forceinline__ int wrap_mod(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+template <typename S, typename C, int T, int FLAGS>
+__global__ void __launch_bounds__(256) k_step_multi(StepArgs<C> a)
+{
+    using R = typename Store<S>::raw;
+    using W = typename Store<S>::wide;
+    constexpr bool NT = (FLAGS & 1) != 0;
+    constexpr bool PIPE = (FLAGS & 2) != 0;
+    constexpr bool DPP = (FLAGS & 4) != 0;
+    constexpr uint32_t E = sizeof(R);
+    constexpr int OUT = 64 - 2 * (T - 1);
+    int bid = blockIdx.x;
+    if (a.xcd_remap) bid = remap_xcd(bid, a.nblocks);
+    const int wave = bid * (int)blockDim.y + (int)threadIdx.y;
+    if (wave >= a.nwaves) return;                       // whole waves only
+    const int strip = wave % a.tiles_x, seg = wave / a.tiles_x;
+    const int lane = threadIdx.x;
+    const int xl = strip * OUT + lane - (T - 1);        // unwrapped column
+    const int c = wrap_mod(xl, a.nx);
+    const uint32_t c0 = (uint32_t)c * E;
+    const uint32_t cm = (uint32_t)((c == 0 ? a.nx : c) - 1) * E;
+    const uint32_t cp = (uint32_t)((c + 1 == a.nx) ? 0 : c + 1) * E;
+    const bool writes = lane >= T - 1 && lane <= 64 - T && xl < a.nx;
+    const char *__restrict__ src = (const char *)a.src;
+    char *__restrict__ dst = (char *)a.dst;
+    const uint64_t pb = (uint64_t)a.plane * E;
+    const uint32_t rb = (uint32_t)a.pitch * E;
+    const int y0 = seg * a.tile_h;
+    const int iters = min(a.tile_h, a.ny - y0) + 2 * (T - 1);
+    auto gather = [&](int r, W w[9]) {
+        const int y = wrap_mod(r, a.ny);
+        const int ym = (y == 0 ? a.ny : y) - 1;
+        const int yp = (y + 1 == a.ny) ? 0 : y + 1;
+        gather9<S, NT>(src, pb, (uint32_t)y * rb, (uint32_t)ym * rb, (uint32_t)yp * rb, c0, cm, cp, w);
+    };
+    // outputs of stage p kept for stage p + 1: populations 2, 5, 6 of the row
+    // before the last one produced, and 0, 1, 3, 2, 5, 6 of the last one
+    W up[T > 1 ? T - 1 : 1][3], mid[T > 1 ? T - 1 : 1][6];
+    W w[9], ahead[9];
+    const int r_first = y0 - (T - 1);
+    if constexpr (PIPE) gather(r_first, ahead);
+    for (int j = 0; j < iters; ++j) {
+        const int r = r_first + j;                      // row of stage 0
+        if constexpr (PIPE) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) w[i] = ahead[i];
+            if (j + 1 < iters) gather(r + 1, ahead);
+        } else {
+            gather(r, w);
+        }
+        cell_update<S, C>(w, a.r, a.scale, a.inv_scale);
+#pragma unroll
+        for (int p = 1; p < T; ++p) {
+            // w holds stage p-1's output, row r - p + 1
+#pragma unroll
+            for (int i = 0; i < 9; ++i) w[i] = round_trip<S>(w[i]);
+            W in[9];
+            const bool active = j >= 2 * p;             // wave-uniform
+            if (active) {
+                in[0] = mid[p - 1][0];
+                in[1] = from_left<DPP>(mid[p - 1][1]);
+                in[3] = from_right<DPP>(mid[p - 1][2]);
+                in[2] = up[p - 1][0];
+                in[5] = from_left<DPP>(up[p - 1][1]);
+                in[6] = from_right<DPP>(up[p - 1][2]);
+                in[4] = w[4];
+                in[7] = from_right<DPP>(w[7]);
+                in[8] = from_left<DPP>(w[8]);
+            }
+            up[p - 1][0] = mid[p - 1][3];
+            up[p - 1][1] = mid[p - 1][4];
+            up[p - 1][2] = mid[p - 1][5];
+            mid[p - 1][0] = w[0];
+            mid[p - 1][1] = w[1];
+            mid[p - 1][2] = w[3];
+            mid[p - 1][3] = w[2];
+            mid[p - 1][4] = w[5];
+            mid[p - 1][5] = w[6];
+            if (!active) break;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) w[i] = in[i];
+            cell_update<S, C>(w, a.r, a.scale, a.inv_scale);
+            if (p == T - 1 && writes) store9<S>(dst, pb, (uint32_t)(r - (T - 1)) * rb + c0, w);
         }
     }
 }
@@ -764,7 +918,33 @@ hipError_t launch_step_typed(const View &v, const void *src, void *dst, const lb
     a.r = make_relax<C>(v);
     a.scale = (float)v.scale;
     a.inv_scale = (float)v.inv_scale;
+    a.nwaves = 0;
+    a.pad_ = 0;
+    if (cfg.variant >= 8) {
+        // strips of 64 - 2(T-1) output columns, segments of `rows` rows, one wave each
+        const int T = cfg.variant - 6;
+        a.tiles_x = (v.nx + (64 - 2 * (T - 1)) - 1) / (64 - 2 * (T - 1));
+        a.tile_h = cfg.rows;
+        const int segs = (v.ny + cfg.rows - 1) / cfg.rows;
+        a.nwaves = a.tiles_x * segs;
+        a.nblocks = (a.nwaves + cfg.block_y - 1) / cfg.block_y;
+    }
     const dim3 grid(a.nblocks), block(cfg.block_x, cfg.block_y);
+    if (cfg.variant >= 8) {
+        switch ((cfg.variant - 8) * 8 + cfg.flags) {
+#define LBM_MULTI(T_, F_)                                                                    \
+    case (T_ - 2) * 8 + F_: hipLaunchKernelGGL((k_step_multi<S, C, T_, F_>), grid, block, 0, st, a); break;
+#define LBM_MULTI_T(T_) LBM_MULTI(T_, 0) LBM_MULTI(T_, 1) LBM_MULTI(T_, 2) LBM_MULTI(T_, 3) \
+                        LBM_MULTI(T_, 4) LBM_MULTI(T_, 5) LBM_MULTI(T_, 6) LBM_MULTI(T_, 7)
+        LBM_MULTI_T(2)
+        LBM_MULTI_T(3)
+        LBM_MULTI_T(4)
+#undef LBM_MULTI_T
+#undef LBM_MULTI
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     const bool nt = cfg.flags & 1, pipe = cfg.flags & 2;
     switch (cfg.variant * 4 + (pipe ? 2 : 0) + (nt ? 1 : 0)) {
     case 0: hipLaunchKernelGGL((k_step_v1<S, C, 0>), grid, block, 0, st, a); break;
@@ -883,8 +1063,15 @@ size_t storage_bytes(int32_t storage)
     }
 }
 
+int steps_per_launch(const lbm_launch &cfg) { return cfg.variant >= 8 && cfg.variant <= 10 ? cfg.variant - 6 : 1; }
+
 bool step_shape_supported(const View &v, const lbm_launch &cfg)
 {
+    if (cfg.variant >= 8 && cfg.variant <= 10) {
+        // several steps per pass: one wave per strip and segment
+        return cfg.block_x == 64 && cfg.block_y >= 1 && cfg.block_y <= 4 && cfg.rows >= 1 &&
+               cfg.rows <= 4096 && (cfg.xcd_remap == 0 || cfg.xcd_remap == 1) && cfg.flags >= 0 && cfg.flags <= 7;
+    }
     if (cfg.variant < 0 || cfg.variant > 7) return false;
     if (cfg.block_x < 1 || cfg.block_y < 1 || cfg.rows < 1 || cfg.rows > 64) return false;
     if (cfg.block_x * cfg.block_y > 1024 || cfg.block_x * cfg.block_y < 64) return false;

@@ -151,9 +151,17 @@ class Lattice:
         _lib.lbm_set_launch(self._h, c)
         return self
 
+    @property
+    def steps_per_launch(self):
+        """Steps one launch of the current shape advances."""
+        return _lib.lbm_steps_per_launch(_lib.lbm_get_launch(self._h))
+
     def tune(self, reps=10):
+        """Selects the launch shape with the least time per step; returns
+        (shape, microseconds per step)."""
         c, us = _lib.lbm_tune(self._h, reps)
         return c.as_dict(), us
 
     def time_launches(self, n):
+        """Microseconds per launch of the current shape (steps_per_launch steps)."""
         return _lib.lbm_time_launches(self._h, n)

@@ -117,7 +117,7 @@ def test_create_checks_workspace_and_call_order_without_touching_the_device():
         # launch shapes are validated on the host
         assert _lib.lbm_get_launch(h).block_x > 0
         with pytest.raises(_lib.LbmError):
-            _lib.lbm_set_launch(h, _lib.lbm_launch(9, 64, 4, 1, 1, 0))
+            _lib.lbm_set_launch(h, _lib.lbm_launch(11, 64, 4, 1, 1, 0))
         with pytest.raises(_lib.LbmError):
             _lib.lbm_set_launch(h, _lib.lbm_launch(0, 2048, 1, 1, 1, 0))
         _lib.lbm_set_launch(h, _lib.lbm_launch(2, 64, 4, 2, 0, 0))        # 64 % 4 == 0
@@ -134,6 +134,30 @@ def test_vector_variants_need_divisible_rows():
         _lib.lbm_set_launch(h, _lib.lbm_launch(1, 64, 4, 1, 1, 0))         # 66 % 2 == 0
         with pytest.raises(_lib.LbmError):
             _lib.lbm_set_launch(h, _lib.lbm_launch(2, 64, 4, 1, 1, 0))     # 66 % 4 != 0
+    finally:
+        _lib.lbm_destroy(h)
+
+
+def test_multi_step_shapes_are_validated_and_report_their_steps():
+    d = desc(nx=66)
+    fake = 1 << 32
+    h = _lib.lbm_create(d, fake, _lib.lbm_workspace_bytes(d), 0)
+    try:
+        for variant, steps in [(0, 1), (4, 1), (7, 1), (8, 2), (9, 3), (10, 4)]:
+            assert _lib.lbm_steps_per_launch(_lib.lbm_launch(variant, 64, 1, 16, 1, 0)) == steps
+        _lib.lbm_set_launch(h, _lib.lbm_launch(9, 64, 4, 4096, 0, 7))
+        assert _lib.lbm_get_launch(h).variant == 9
+        for bad in [(8, 128, 1, 16, 1, 0),      # one wave along x
+                    (8, 64, 5, 16, 1, 0),       # at most 4 waves per workgroup
+                    (8, 64, 1, 0, 1, 0),        # rows >= 1
+                    (10, 64, 1, 4097, 1, 0),    # rows <= 4096
+                    (9, 64, 1, 16, 2, 0),       # xcd_remap 0 or 1
+                    (10, 64, 1, 16, 1, 8),      # flags 0..7
+                    (4, 64, 1, 1, 1, 4),        # bit 2 only for several steps per launch
+                    (11, 64, 1, 16, 1, 0)]:     # no such variant
+            with pytest.raises(_lib.LbmError):
+                _lib.lbm_set_launch(h, _lib.lbm_launch(*bad))
+        assert _lib.lbm_get_launch(h).variant == 9
     finally:
         _lib.lbm_destroy(h)
 

@@ -84,7 +84,16 @@ def test_all_launch_shapes_give_identical_results(storage):
                    dict(variant=4, block_x=1024, block_y=1, rows=1, xcd_remap=1, flags=3),
                    dict(variant=5, block_x=256, block_y=1, rows=2, xcd_remap=0, flags=1),
                    dict(variant=6, block_x=64, block_y=4, rows=1, xcd_remap=1, flags=0),
-                   dict(variant=7, block_x=16, block_y=4, rows=3, xcd_remap=0, flags=1)]:
+                   dict(variant=7, block_x=16, block_y=4, rows=3, xcd_remap=0, flags=1),
+                   # several steps per launch (25 = passes + left-over single steps)
+                   dict(variant=8, block_x=64, block_y=1, rows=16, xcd_remap=0, flags=0),
+                   dict(variant=8, block_x=64, block_y=4, rows=64, xcd_remap=1, flags=3),
+                   dict(variant=9, block_x=64, block_y=2, rows=7, xcd_remap=0, flags=2),
+                   dict(variant=10, block_x=64, block_y=3, rows=100, xcd_remap=1, flags=1),
+                   dict(variant=10, block_x=64, block_y=1, rows=1, xcd_remap=0, flags=0),
+                   dict(variant=8, block_x=64, block_y=2, rows=32, xcd_remap=1, flags=4),
+                   dict(variant=9, block_x=64, block_y=4, rows=5, xcd_remap=0, flags=7),
+                   dict(variant=10, block_x=64, block_y=1, rows=128, xcd_remap=1, flags=6)]:
         lat = lattice(nx, ny, s, storage, u0=(0.02, 0.01))
         lat.set_launch(**launch)
         f = lat.init(rho, ux, uy).step(25).populations()
@@ -92,6 +101,24 @@ def test_all_launch_shapes_give_identical_results(storage):
             ref = f
         else:
             assert torch.equal(ref, f), launch
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("nx,ny", [(1, 1), (5, 3), (63, 9), (62, 2), (130, 70), (200, 5), (3, 130)])
+def test_several_steps_per_launch_equal_single_steps(storage, nx, ny):
+    # tiny, ragged and single-strip lattices; 7 steps leave 1, 1 and 3
+    # single steps over for T = 2, 3, 4
+    rho, ux, uy = fields(nx, ny, 5, (0.02, -0.01))
+    s = ll_rates()
+    kw = dict(u0=(0.02, -0.01), scale_exp=22 if storage in ("f16", "bf16") else None)
+    ref = lattice(nx, ny, s, storage, **kw).init(rho, ux, uy).step(7).populations()
+    for variant, rows, flags in [(8, 4, 0), (9, 1, 3), (10, 64, 2), (8, 3, 4), (9, 16, 5), (10, 2, 6)]:
+        lat = lattice(nx, ny, s, storage, **kw)
+        lat.set_launch(variant=variant, block_x=64, block_y=2, rows=rows, xcd_remap=1, flags=flags)
+        assert lat.steps_per_launch == variant - 6
+        lat.init(rho, ux, uy).step(7)
+        assert lat.t == 7
+        assert torch.equal(lat.populations(), ref), (variant, rows, flags)
 
 
 def test_tune_and_timing_leave_the_state_unchanged():
