@@ -125,7 +125,9 @@ typedef struct lbm_lattice lbm_lattice;
  *             0, 8, 9, 10) or next chunk's (variant 4) loads before colliding
  *             the current cells (variants 0, 4, 8, 9, 10 only); bit 2
  *             (variants 8, 9, 10 only): move values between neighbouring
- *             lanes with DPP whole-wave shifts instead of LDS shuffles.
+ *             lanes with DPP whole-wave shifts instead of LDS shuffles; bit 3
+ *             (variants 8, 9, 10 only, not with bit 1): issue the loads two
+ *             rows ahead.
  * Every shape produces bit-identical results. */
 typedef struct lbm_launch {
     int32_t variant;

@@ -143,7 +143,7 @@ std::vector<lbm_launch> multi_candidates(const View &v)
     for (int var = 8; var <= 10; ++var)
         for (int by : {1, 2, 4})
             for (int rows : {32, 64, 128, 256})
-                for (int flags : {0, 2, 4, 6})
+                for (int flags : {0, 4, 6, 12})
                     for (int remap = 0; remap < 2; ++remap) {
                         lbm_launch c{};
                         c.variant = var;

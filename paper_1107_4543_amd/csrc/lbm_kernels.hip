@@ -12,6 +12,8 @@
 // v_x != 0 is misaligned by one element.
 #include <math.h>
 
+#include <type_traits>
+
 #include "lbm_device.hpp"
 #include "lbm_internal.hpp"
 
@@ -474,8 +476,9 @@ __global__ void __launch_bounds__(256) k_step_multi(StepArgs<C> a)
     using R = typename Store<S>::raw;
     using W = typename Store<S>::wide;
     constexpr bool NT = (FLAGS & 1) != 0;
-    constexpr bool PIPE = (FLAGS & 2) != 0;
     constexpr bool DPP = (FLAGS & 4) != 0;
+    // rows of stage-0 loads issued ahead of the row being collided
+    constexpr int AHEAD = (FLAGS & 8) ? 2 : ((FLAGS & 2) ? 1 : 0);
     constexpr uint32_t E = sizeof(R);
     constexpr int OUT = 64 - 2 * (T - 1);
     int bid = blockIdx.x;
@@ -505,15 +508,27 @@ __global__ void __launch_bounds__(256) k_step_multi(StepArgs<C> a)
     // outputs of stage p kept for stage p + 1: populations 2, 5, 6 of the row
     // before the last one produced, and 0, 1, 3, 2, 5, 6 of the last one
     W up[T > 1 ? T - 1 : 1][3], mid[T > 1 ? T - 1 : 1][6];
-    W w[9], ahead[9];
+    W ahead[AHEAD > 0 ? AHEAD : 1][9];
     const int r_first = y0 - (T - 1);
-    if constexpr (PIPE) gather(r_first, ahead);
-    for (int j = 0; j < iters; ++j) {
-        const int r = r_first + j;                      // row of stage 0
-        if constexpr (PIPE) {
 #pragma unroll
-            for (int i = 0; i < 9; ++i) w[i] = ahead[i];
-            if (j + 1 < iters) gather(r + 1, ahead);
+    for (int d = 0; d < AHEAD; ++d)
+        if (d < iters) gather(r_first + d, ahead[d]);
+    // One row of the pipeline.  Before iteration 2(T-1) the later stages
+    // have no rows yet and stop early (STEADY = false); afterwards every
+    // stage runs and the body has no branches, so the loop can be unrolled
+    // and the row rotation becomes register renaming.
+    auto row = [&](int j, auto steady) {
+        constexpr bool STEADY = decltype(steady)::value;
+        const int r = r_first + j;                      // row of stage 0
+        W w[9];
+        if constexpr (AHEAD > 0) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) w[i] = ahead[0][i];
+#pragma unroll
+            for (int d = 0; d + 1 < AHEAD; ++d)
+#pragma unroll
+                for (int i = 0; i < 9; ++i) ahead[d][i] = ahead[d + 1][i];
+            if (j + AHEAD < iters) gather(r + AHEAD, ahead[AHEAD - 1]);
         } else {
             gather(r, w);
         }
@@ -524,7 +539,7 @@ __global__ void __launch_bounds__(256) k_step_multi(StepArgs<C> a)
 #pragma unroll
             for (int i = 0; i < 9; ++i) w[i] = round_trip<S>(w[i]);
             W in[9];
-            const bool active = j >= 2 * p;             // wave-uniform
+            const bool active = STEADY || j >= 2 * p;   // wave-uniform
             if (active) {
                 in[0] = mid[p - 1][0];
                 in[1] = from_left<DPP>(mid[p - 1][1]);
@@ -551,7 +566,17 @@ __global__ void __launch_bounds__(256) k_step_multi(StepArgs<C> a)
             cell_update<S, C>(w, a.r, a.scale, a.inv_scale);
             if (p == T - 1 && writes) store9<S>(dst, pb, (uint32_t)(r - (T - 1)) * rb + c0, w);
         }
+    };
+    const int pro = min(iters, 2 * (T - 1));
+    for (int j = 0; j < pro; ++j) row(j, std::false_type{});
+    // two rows per trip (the compiler does not unroll loops that hold
+    // cross-lane operations by a runtime count itself)
+    int j = pro;
+    for (; j + 1 < iters; j += 2) {
+        row(j, std::true_type{});
+        row(j + 1, std::true_type{});
     }
+    if (j < iters) row(j, std::true_type{});
 }
 
 // ---- batched step over a pool of lattices ----------------------------------------
@@ -931,11 +956,12 @@ hipError_t launch_step_typed(const View &v, const void *src, void *dst, const lb
     }
     const dim3 grid(a.nblocks), block(cfg.block_x, cfg.block_y);
     if (cfg.variant >= 8) {
-        switch ((cfg.variant - 8) * 8 + cfg.flags) {
+        switch ((cfg.variant - 8) * 16 + cfg.flags) {
 #define LBM_MULTI(T_, F_)                                                                    \
-    case (T_ - 2) * 8 + F_: hipLaunchKernelGGL((k_step_multi<S, C, T_, F_>), grid, block, 0, st, a); break;
+    case (T_ - 2) * 16 + F_: hipLaunchKernelGGL((k_step_multi<S, C, T_, F_>), grid, block, 0, st, a); break;
 #define LBM_MULTI_T(T_) LBM_MULTI(T_, 0) LBM_MULTI(T_, 1) LBM_MULTI(T_, 2) LBM_MULTI(T_, 3) \
-                        LBM_MULTI(T_, 4) LBM_MULTI(T_, 5) LBM_MULTI(T_, 6) LBM_MULTI(T_, 7)
+                        LBM_MULTI(T_, 4) LBM_MULTI(T_, 5) LBM_MULTI(T_, 6) LBM_MULTI(T_, 7) \
+                        LBM_MULTI(T_, 8) LBM_MULTI(T_, 9) LBM_MULTI(T_, 12) LBM_MULTI(T_, 13)
         LBM_MULTI_T(2)
         LBM_MULTI_T(3)
         LBM_MULTI_T(4)
@@ -1070,7 +1096,8 @@ bool step_shape_supported(const View &v, const lbm_launch &cfg)
     if (cfg.variant >= 8 && cfg.variant <= 10) {
         // several steps per pass: one wave per strip and segment
         return cfg.block_x == 64 && cfg.block_y >= 1 && cfg.block_y <= 4 && cfg.rows >= 1 &&
-               cfg.rows <= 4096 && (cfg.xcd_remap == 0 || cfg.xcd_remap == 1) && cfg.flags >= 0 && cfg.flags <= 7;
+               cfg.rows <= 4096 && (cfg.xcd_remap == 0 || cfg.xcd_remap == 1) && cfg.flags >= 0 &&
+               cfg.flags <= 13 && !((cfg.flags & 8) && (cfg.flags & 2));
     }
     if (cfg.variant < 0 || cfg.variant > 7) return false;
     if (cfg.block_x < 1 || cfg.block_y < 1 || cfg.rows < 1 || cfg.rows > 64) return false;

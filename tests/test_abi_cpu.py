@@ -152,7 +152,8 @@ def test_multi_step_shapes_are_validated_and_report_their_steps():
                     (8, 64, 1, 0, 1, 0),        # rows >= 1
                     (10, 64, 1, 4097, 1, 0),    # rows <= 4096
                     (9, 64, 1, 16, 2, 0),       # xcd_remap 0 or 1
-                    (10, 64, 1, 16, 1, 8),      # flags 0..7
+                    (10, 64, 1, 16, 1, 14),     # flags 0..13
+                    (10, 64, 1, 16, 1, 10),     # one and two rows ahead together
                     (4, 64, 1, 1, 1, 4),        # bit 2 only for several steps per launch
                     (11, 64, 1, 16, 1, 0)]:     # no such variant
             with pytest.raises(_lib.LbmError):
