@@ -143,17 +143,16 @@ std::vector<lbm_launch> multi_candidates(const View &v)
     for (int var = 8; var <= 10; ++var)
         for (int by : {1, 2, 4})
             for (int rows : {32, 64, 128, 256})
-                for (int flags : {0, 4, 6, 12})
-                    for (int remap = 0; remap < 2; ++remap) {
-                        lbm_launch c{};
-                        c.variant = var;
-                        c.block_x = 64;
-                        c.block_y = by;
-                        c.rows = rows;
-                        c.xcd_remap = remap;
-                        c.flags = flags;
-                        if (rows <= 2 * v.ny && lbm::step_shape_supported(v, c)) out.push_back(c);
-                    }
+                for (int flags : {0, 2, 4, 6, 8, 12}) {
+                    lbm_launch c{};
+                    c.variant = var;
+                    c.block_x = 64;
+                    c.block_y = by;
+                    c.rows = rows;
+                    c.xcd_remap = 1;
+                    c.flags = flags;
+                    if (rows <= 2 * v.ny && lbm::step_shape_supported(v, c)) out.push_back(c);
+                }
     return out;
 }
 

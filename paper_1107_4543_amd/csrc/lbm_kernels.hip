@@ -517,18 +517,19 @@ __global__ void __launch_bounds__(256) k_step_multi(StepArgs<C> a)
     // have no rows yet and stop early (STEADY = false); afterwards every
     // stage runs and the body has no branches, so the loop can be unrolled
     // and the row rotation becomes register renaming.
-    auto row = [&](int j, auto steady) {
+    // Row j takes its stage-0 values from slot j % AHEAD and refills that
+    // slot with row j + AHEAD: no register is copied while its load is in
+    // flight, so the waits cover only the loads issued AHEAD rows earlier.
+    auto row = [&](int j, auto steady, W(&slot)[9]) {
         constexpr bool STEADY = decltype(steady)::value;
         const int r = r_first + j;                      // row of stage 0
         W w[9];
         if constexpr (AHEAD > 0) {
 #pragma unroll
-            for (int i = 0; i < 9; ++i) w[i] = ahead[0][i];
-#pragma unroll
-            for (int d = 0; d + 1 < AHEAD; ++d)
-#pragma unroll
-                for (int i = 0; i < 9; ++i) ahead[d][i] = ahead[d + 1][i];
-            if (j + AHEAD < iters) gather(r + AHEAD, ahead[AHEAD - 1]);
+            for (int i = 0; i < 9; ++i) w[i] = slot[i];
+            // unconditional (rows past the segment wrap and are never
+            // used): no branch, so the waits for these loads stay exact
+            gather(r + AHEAD, slot);
         } else {
             gather(r, w);
         }
@@ -567,16 +568,27 @@ __global__ void __launch_bounds__(256) k_step_multi(StepArgs<C> a)
             if (p == T - 1 && writes) store9<S>(dst, pb, (uint32_t)(r - (T - 1)) * rb + c0, w);
         }
     };
+    // Two rows per trip (the compiler does not unroll loops that hold
+    // cross-lane operations by a runtime count itself); the even row of a
+    // trip uses slot 0, the odd one slot AHEAD - 1.  The prologue has an even
+    // number of rows unless the whole segment is shorter.
+    constexpr int S1 = AHEAD > 1 ? 1 : 0;
     const int pro = min(iters, 2 * (T - 1));
-    for (int j = 0; j < pro; ++j) row(j, std::false_type{});
-    // two rows per trip (the compiler does not unroll loops that hold
-    // cross-lane operations by a runtime count itself)
-    int j = pro;
-    for (; j + 1 < iters; j += 2) {
-        row(j, std::true_type{});
-        row(j + 1, std::true_type{});
+    int j = 0;
+    for (; j + 1 < pro; j += 2) {
+        row(j, std::false_type{}, ahead[0]);
+        row(j + 1, std::false_type{}, ahead[S1]);
     }
-    if (j < iters) row(j, std::true_type{});
+    if (j < pro) {
+        // odd prologue: the segment ends inside it (j + 1 == pro == iters)
+        row(j, std::false_type{}, ahead[0]);
+        ++j;
+    }
+    for (; j + 1 < iters; j += 2) {
+        row(j, std::true_type{}, ahead[0]);
+        row(j + 1, std::true_type{}, ahead[S1]);
+    }
+    if (j < iters) row(j, std::true_type{}, ahead[0]);
 }
 
 // ---- batched step over a pool of lattices ----------------------------------------
