@@ -48,10 +48,16 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def read_traffic(workload, storage):
-    """Measured HBM bytes per launch from the committed counter summary, or
-    None when absent or taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_step_{storage}_{workload}.txt")
+VALU_PEAK = 256 * 4 * 16 * 2.4e9      # VALU lane-instructions per second (non-packed)
+
+
+def read_profile(workload, storage, launch):
+    """Key/value lines of the committed counter summary for this kernel, or
+    None when absent, taken on a different kernel source, or on another
+    kernel (variant and flags select the kernel; the summary names the shape
+    it was taken with)."""
+    kernel = "step_multi" if launch["variant"] >= 8 else "step"
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{storage}_{workload}.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -61,10 +67,25 @@ def read_traffic(workload, storage):
             kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256") != kernel_source_hash():
         return None
+    shape = kv.get("launch", "").split(",")
+    if len(shape) != 6 or int(shape[0]) != launch["variant"] or int(shape[5]) != launch["flags"]:
+        return None
+    return kv
+
+
+def read_traffic(workload, storage, launch):
+    """Measured HBM bytes per launch (see read_profile), or None."""
+    kv = read_profile(workload, storage, launch)
     try:
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv["traffic_bytes_per_launch"]) if kv else None
     except (KeyError, ValueError):
         return None
+
+
+# Launch shapes lbm_tune selected for the 4096^2 wave workload on MI355X
+# (variant 10: four steps per pass); --tune searches again.
+DEFAULT_LAUNCH = {"f32": "10,64,1,256,1,2", "f16": "10,64,4,32,1,2", "bf16": "10,64,4,32,1,6",
+                  "f64": "10,64,4,32,1,12"}
 
 
 def build_waves4096(storage):
@@ -331,9 +352,11 @@ def main():
     ap.add_argument("--rates", default="10,30,100,300,1000", help="serve: arrival rates (jobs/s)")
     ap.add_argument("--jobs", type=int, default=40, help="serve: jobs per rate")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget for admitted jobs")
-    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--no-tune", action="store_true", help="use the library's default one-step launch shape")
+    ap.add_argument("--tune", action="store_true", help="search the launch shape with lbm_tune before timing")
     ap.add_argument("--launch", default=None,
-                    help="fixed launch shape variant,block_x,block_y,rows,xcd_remap,flags (no tuning)")
+                    help="launch shape variant,block_x,block_y,rows,xcd_remap,flags (default: the recorded "
+                         "tuned shape for the storage type)")
     ap.add_argument("--probe", choices=["copy"], default=None,
                     help="run only the device-to-device copy probe")
     ap.add_argument("--probe-bytes", type=int, default=1 << 30)
@@ -363,10 +386,10 @@ def main():
         return
 
     lat, cfg, rates, fields1, w = build_waves4096(args.storage)
-    if args.launch:
-        lat.set_launch(**parse_launch(args.launch))
-    elif not args.no_tune:
+    if args.tune:
         lat.tune(reps=5)
+    elif not args.no_tune:
+        lat.set_launch(**parse_launch(args.launch or DEFAULT_LAUNCH[args.storage]))
     cfg["launch"] = lat.launch
 
     stream = lat.stream
@@ -392,7 +415,7 @@ def main():
     us_per_launch = 1e3 * ms / launches
     alg_bytes = 2 * 9 * STORE_BYTES[args.storage] * cells
     achieved = alg_bytes / (us_per_launch * 1e-6) / 1e9
-    traffic = read_traffic("waves4096", args.storage)
+    traffic = read_traffic("waves4096", args.storage, lat.launch)
 
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
@@ -406,6 +429,16 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes, "steps_per_launch": spl,
                      "launches": launches, "avg_launch_us": round(us_per_launch, 3)},
     }
+    kv = read_profile("waves4096", args.storage, lat.launch)
+    if kv and "valu_lane_instructions_per_update" in kv:
+        # the kernel moves a quarter of the one-step bytes per update, so its
+        # limit is instruction issue: VALU lane-instructions per update (from
+        # the compiled loop, see the profile) times updates per second
+        per_lu = float(kv["valu_lane_instructions_per_update"])
+        out["roofline"]["valu_issue"] = {"lane_instructions_per_update": per_lu,
+                                         "achieved": round(per_lu * mlups * 1e6 / 1e12, 2),
+                                         "peak": round(VALU_PEAK / 1e12, 2), "unit": "T lane-instr/s",
+                                         "frac": round(per_lu * mlups * 1e6 / VALU_PEAK, 4)}
     out["context"] = {"copy_probe": copy_probe(alg_bytes // 2, 10), "device": torch.cuda.get_device_name(0)}
     if args.cpu_budget > 0:
         out["cpu_baseline"] = cpu_baseline(rates, fields1, lat.nx, lat.ny, w["u0x"], args.cpu_budget)

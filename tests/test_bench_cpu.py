@@ -1,0 +1,55 @@
+"""Host-side pieces of bench.py: the one-GPU guard, launch parsing, the
+recorded default launch shapes, and the lookup of committed counter
+summaries (which must name the kernel, flags and source they were taken on)."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_1107_4543_amd import _lib  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_launch_parsing_and_default_shapes_are_valid():
+    assert bench.parse_launch("10,64,1,256,1,2") == dict(variant=10, block_x=64, block_y=1, rows=256,
+                                                          xcd_remap=1, flags=2)
+    with pytest.raises(SystemExit):
+        bench.parse_launch("1,2,3")
+    d = _lib.lbm_desc()
+    d.nx = d.ny = 4096
+    d.compute = _lib.LBM_COMPUTE_F32
+    d.s_e, d.s_eps, d.s_q, d.s_nu = 1.9, 1.9, 1.9, 1.9
+    d.rho0, d.u0x, d.u0y = 1.0, 0.0, 0.0
+    d.scale_exp = _lib.LBM_SCALE_AUTO
+    for storage, text in bench.DEFAULT_LAUNCH.items():
+        d.storage = _lib.STORAGE[storage]
+        d.compute = _lib.LBM_COMPUTE_F64 if storage == "f64" else _lib.LBM_COMPUTE_F32
+        h = _lib.lbm_create(d, 1 << 32, _lib.lbm_workspace_bytes(d), 0)
+        try:
+            _lib.lbm_set_launch(h, _lib.lbm_launch(*bench.parse_launch(text).values()))
+            assert _lib.lbm_steps_per_launch(_lib.lbm_get_launch(h)) == 4
+        finally:
+            _lib.lbm_destroy(h)
+
+
+def test_profile_lookup_checks_kernel_and_source():
+    launch = bench.parse_launch(bench.DEFAULT_LAUNCH["f32"])
+    kv = bench.read_profile("waves4096", "f32", launch)
+    if kv is not None:                  # committed summary taken on the current source
+        assert kv["kernel_source_sha256"] == bench.kernel_source_hash()
+        t = bench.read_traffic("waves4096", "f32", launch)
+        assert 1.0 <= t / float(kv["algorithmic_bytes_per_launch"]) < 1.5
+    other = dict(launch, flags=launch["flags"] ^ 4)
+    assert bench.read_traffic("waves4096", "f32", other) is None
+    assert bench.read_traffic("waves4096", "f16", launch) is None or os.path.exists(
+        os.path.join(ROOT, "profiles", "traffic_step_multi_f16_waves4096.txt"))
