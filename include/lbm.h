@@ -246,9 +246,13 @@ LBM_API int32_t lbm_steps_per_launch(const lbm_launch *cfg);
 /* ---- pools: many lattices advanced together ------------------------------
  *
  * A pool advances its members (lattices of any size, rates and storage)
- * with one persistent launch per storage class and step; step loops of
- * power-of-two lengths up to graph_steps are recorded once as HIP graphs and
- * replayed (lbm_pool_step(n) runs n steps as a few such replays).  Each
+ * with persistent launches per storage class: with steps_per_launch T > 1
+ * one launch advances every member by T steps (strip tasks of the
+ * several-steps-per-pass kernel, see lbm_launch variants 8-10) and a member
+ * whose remaining count is not a multiple of T takes its last steps in
+ * one-step launches; step loops of power-of-two lengths up to graph_steps
+ * are recorded once as HIP graphs and replayed (lbm_pool_step(n) runs n
+ * steps as a few such replays).  Each
  * member carries its own step count: a member added with nsteps stops after
  * exactly nsteps steps, independently of the others, and is then returned by
  * lbm_pool_poll.  Members join and leave between lbm_pool_step calls
@@ -264,17 +268,31 @@ LBM_API int32_t lbm_steps_per_launch(const lbm_launch *cfg);
 typedef struct lbm_pool lbm_pool;
 
 /* Launch shape of a pool.
- *   tile_cells   target cells per tile (a tile is whole rows of one member:
- *                max(1, tile_cells / nx) rows), 64 .. 2^22
- *   block        threads per workgroup, multiple of 64, 64 .. 1024
- *   grid         workgroups of the persistent launch, 1 .. 2^20
+ *   tile_cells   target cells per tile of the one-step launch (a tile is
+ *                whole rows of one member: max(1, tile_cells / nx) rows),
+ *                64 .. 2^22
+ *   block        threads per workgroup of the one-step launch, multiple of
+ *                64, 64 .. 1024
+ *   grid         workgroups of a persistent launch (both kinds), 1 .. 2^20
  *   graph_steps  longest recorded step loop (rounded down to a power of
- *                two when used), 1 .. 1024 */
+ *                two when used), 1 .. 1024
+ *   steps_per_launch  T = 1, 2 or 4; T > 1 adds strip tasks of 64 - 2(T-1)
+ *                columns and seg_rows rows, one wave each
+ *   seg_rows     rows of a strip task, 1 .. 4096
+ *   waves        waves per workgroup of the T-step launch, 1 .. 4
+ *   flags        T-step kernel flags as in lbm_launch (0 .. 13, not bits 1
+ *                and 3 together)
+ * The tile table holds the one-step tiles and, for T > 1, the strip tasks
+ * of every unfinished member. */
 typedef struct lbm_pool_shape {
     int32_t tile_cells;
     int32_t block;
     int32_t grid;
     int32_t graph_steps;
+    int32_t steps_per_launch;
+    int32_t seg_rows;
+    int32_t waves;
+    int32_t flags;
 } lbm_pool_shape;
 
 /* Device bytes of a pool's member and tile tables; 0 if out of range
@@ -307,10 +325,12 @@ LBM_API int64_t lbm_pool_remaining(const lbm_pool *pool, const lbm_lattice *lat)
 LBM_API lbm_status lbm_pool_get_shape(const lbm_pool *pool, lbm_pool_shape *out);
 /* LBM_E_INVAL for an invalid shape, LBM_E_NOMEM if the tiles would not fit. */
 LBM_API lbm_status lbm_pool_set_shape(lbm_pool *pool, const lbm_pool_shape *shape);
-/* Times reps launches of one step of every member (states unchanged; syncs). */
+/* Times reps launches that advance every member by one launch's worth of
+ * steps (steps_per_launch; states unchanged; syncs); avg_us per launch. */
 LBM_API lbm_status lbm_pool_time_launches(lbm_pool *pool, int32_t reps, double *avg_us);
-/* Times tile sizes, workgroup sizes and grid sizes on the current members,
- * keeps the fastest (states unchanged; syncs). */
+/* Times tile sizes, workgroup sizes, grid sizes and T-step strip shapes on
+ * the current members, keeps the one with the least time per step (states
+ * unchanged; syncs); best_us is per step. */
 LBM_API lbm_status lbm_pool_tune(lbm_pool *pool, int32_t reps, lbm_pool_shape *best, double *best_us);
 
 #ifdef __cplusplus

@@ -50,7 +50,9 @@ class lbm_launch(ctypes.Structure):
 
 class lbm_pool_shape(ctypes.Structure):
     _fields_ = [("tile_cells", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("grid", ctypes.c_int32), ("graph_steps", ctypes.c_int32)]
+                ("grid", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
+                ("steps_per_launch", ctypes.c_int32), ("seg_rows", ctypes.c_int32),
+                ("waves", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -64,6 +64,7 @@ struct PoolMember {
     int32_t nx, ny, pitch, cur0;   // cur0: buffer holding the state when added
     int64_t plane;
     int64_t t_done, t_target;      // steps done since added / steps requested
+    int64_t flips;                 // launches since added (buffer swaps)
     Relax<float> rf;
     Relax<double> rd;
     float scale, inv_scale;
@@ -78,8 +79,22 @@ struct PoolTile {
 };
 
 struct PoolHeader {
-    int32_t begin[kClasses], end[kClasses];   // tile range of each class
+    int32_t begin[kClasses], end[kClasses];     // one-step tiles of each class
+    int32_t mbegin[kClasses], mend[kClasses];   // T-step strip tasks of each class
 };
+
+// Launch schedule of a recorded chunk of kk steps with T steps per T-step
+// launch: kk / T T-step launches, then the one-step launches that members
+// finishing inside the chunk need.  A member with rem steps left takes
+// q = min(rem / T, kk / T) T-step launches and span - q T one-step launches,
+// span = min(rem, kk); its source buffer alternates with every launch.
+__host__ __device__ inline int chunk_multi_launches(int kk, int T) { return T > 1 && kk >= T ? kk / T : 0; }
+__host__ __device__ inline int chunk_single_launches(int kk, int T) { return T > 1 && kk >= T ? T - 1 : kk; }
+__host__ __device__ inline int64_t member_multi(int64_t rem, int kk, int T)
+{
+    const int64_t a = rem / T, b = chunk_multi_launches(kk, T);
+    return T > 1 ? (a < b ? a : b) : 0;
+}
 
 // Sets the text returned by lbm_last_error() on the calling thread.
 void set_error_text(const char *msg);
@@ -87,13 +102,18 @@ void set_error_text(const char *msg);
 Relax<float> relax_f32(const View &v);
 Relax<double> relax_f64(const View &v);
 
-// One step (index k within the current chunk) of every active member of class cls.
-hipError_t launch_pool_step(int cls, const PoolHeader *hdr, const PoolMember *mem, const PoolTile *tiles, int k,
-                            int grid, int block, hipStream_t st);
-// t_done += min(kk, t_target - t_done) for members [0, nmem).
-hipError_t launch_pool_commit(PoolMember *mem, int nmem, int kk, hipStream_t st);
-// Kernel entry points and argument layout for graph nodes.
+// One-step launch i of a chunk of kk steps (schedule above) of every active
+// member of class cls.
+hipError_t launch_pool_step(int cls, const PoolHeader *hdr, const PoolMember *mem, const PoolTile *tiles, int i,
+                            int kk, int T, int grid, int block, hipStream_t st);
+// T-step launch j of a chunk of every active member of class cls.
+hipError_t launch_pool_multi(int cls, int T, int flags, const PoolHeader *hdr, const PoolMember *mem,
+                             const PoolTile *tiles, int j, int grid, int waves, hipStream_t st);
+// t_done += span and flips += q + span - q T (schedule above) for members [0, nmem).
+hipError_t launch_pool_commit(PoolMember *mem, int nmem, int kk, int T, hipStream_t st);
+// Kernel entry points for graph nodes (nullptr if not instantiated).
 void *pool_step_kernel(int cls);
+void *pool_multi_kernel(int cls, int T, int flags);
 void *pool_commit_kernel();
 
 }  // namespace lbm

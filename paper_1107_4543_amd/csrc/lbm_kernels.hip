@@ -470,8 +470,12 @@ __device__ __forceinline__ int wrap_mod(int v, int n)
     return v < 0 ? v + n : v;
 }
 
+// T steps of the strip whose output columns start at x0, rows y0 .. y0+len-1
+// of one lattice, by the calling wave (threadIdx.x = lane).
 template <typename S, typename C, int T, int FLAGS>
-__global__ void __launch_bounds__(256) k_step_multi(StepArgs<C> a)
+__device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *__restrict__ dst, int nx, int ny,
+                                           int pitch, int64_t plane, const Relax<C> &relax, float scale,
+                                           float inv_scale, int x0, int y0, int len)
 {
     using R = typename Store<S>::raw;
     using W = typename Store<S>::wide;
@@ -480,29 +484,20 @@ __global__ void __launch_bounds__(256) k_step_multi(StepArgs<C> a)
     // rows of stage-0 loads issued ahead of the row being collided
     constexpr int AHEAD = (FLAGS & 8) ? 2 : ((FLAGS & 2) ? 1 : 0);
     constexpr uint32_t E = sizeof(R);
-    constexpr int OUT = 64 - 2 * (T - 1);
-    int bid = blockIdx.x;
-    if (a.xcd_remap) bid = remap_xcd(bid, a.nblocks);
-    const int wave = bid * (int)blockDim.y + (int)threadIdx.y;
-    if (wave >= a.nwaves) return;                       // whole waves only
-    const int strip = wave % a.tiles_x, seg = wave / a.tiles_x;
     const int lane = threadIdx.x;
-    const int xl = strip * OUT + lane - (T - 1);        // unwrapped column
-    const int c = wrap_mod(xl, a.nx);
+    const int xl = x0 + lane - (T - 1);                 // unwrapped column
+    const int c = wrap_mod(xl, nx);
     const uint32_t c0 = (uint32_t)c * E;
-    const uint32_t cm = (uint32_t)((c == 0 ? a.nx : c) - 1) * E;
-    const uint32_t cp = (uint32_t)((c + 1 == a.nx) ? 0 : c + 1) * E;
-    const bool writes = lane >= T - 1 && lane <= 64 - T && xl < a.nx;
-    const char *__restrict__ src = (const char *)a.src;
-    char *__restrict__ dst = (char *)a.dst;
-    const uint64_t pb = (uint64_t)a.plane * E;
-    const uint32_t rb = (uint32_t)a.pitch * E;
-    const int y0 = seg * a.tile_h;
-    const int iters = min(a.tile_h, a.ny - y0) + 2 * (T - 1);
+    const uint32_t cm = (uint32_t)((c == 0 ? nx : c) - 1) * E;
+    const uint32_t cp = (uint32_t)((c + 1 == nx) ? 0 : c + 1) * E;
+    const bool writes = lane >= T - 1 && lane <= 64 - T && xl < nx;
+    const uint64_t pb = (uint64_t)plane * E;
+    const uint32_t rb = (uint32_t)pitch * E;
+    const int iters = len + 2 * (T - 1);
     auto gather = [&](int r, W w[9]) {
-        const int y = wrap_mod(r, a.ny);
-        const int ym = (y == 0 ? a.ny : y) - 1;
-        const int yp = (y + 1 == a.ny) ? 0 : y + 1;
+        const int y = wrap_mod(r, ny);
+        const int ym = (y == 0 ? ny : y) - 1;
+        const int yp = (y + 1 == ny) ? 0 : y + 1;
         gather9<S, NT>(src, pb, (uint32_t)y * rb, (uint32_t)ym * rb, (uint32_t)yp * rb, c0, cm, cp, w);
     };
     // outputs of stage p kept for stage p + 1: populations 2, 5, 6 of the row
@@ -533,7 +528,7 @@ __global__ void __launch_bounds__(256) k_step_multi(StepArgs<C> a)
         } else {
             gather(r, w);
         }
-        cell_update<S, C>(w, a.r, a.scale, a.inv_scale);
+        cell_update<S, C>(w, relax, scale, inv_scale);
 #pragma unroll
         for (int p = 1; p < T; ++p) {
             // w holds stage p-1's output, row r - p + 1
@@ -564,7 +559,7 @@ __global__ void __launch_bounds__(256) k_step_multi(StepArgs<C> a)
             if (!active) break;
 #pragma unroll
             for (int i = 0; i < 9; ++i) w[i] = in[i];
-            cell_update<S, C>(w, a.r, a.scale, a.inv_scale);
+            cell_update<S, C>(w, relax, scale, inv_scale);
             if (p == T - 1 && writes) store9<S>(dst, pb, (uint32_t)(r - (T - 1)) * rb + c0, w);
         }
     };
@@ -591,18 +586,34 @@ __global__ void __launch_bounds__(256) k_step_multi(StepArgs<C> a)
     if (j < iters) row(j, std::true_type{}, ahead[0]);
 }
 
+template <typename S, typename C, int T, int FLAGS>
+__global__ void __launch_bounds__(256) k_step_multi(StepArgs<C> a)
+{
+    constexpr int OUT = 64 - 2 * (T - 1);
+    int bid = blockIdx.x;
+    if (a.xcd_remap) bid = remap_xcd(bid, a.nblocks);
+    const int wave = bid * (int)blockDim.y + (int)threadIdx.y;
+    if (wave >= a.nwaves) return;                       // whole waves only
+    const int strip = wave % a.tiles_x, seg = wave / a.tiles_x;
+    const int y0 = seg * a.tile_h;
+    strip_pass<S, C, T, FLAGS>((const char *)a.src, (char *)a.dst, a.nx, a.ny, a.pitch, a.plane, a.r, a.scale,
+                               a.inv_scale, strip * OUT, y0, min(a.tile_h, a.ny - y0));
+}
+
 // ---- batched step over a pool of lattices ----------------------------------------
 //
-// One launch advances every active member of one storage class by one step.
-// The grid is persistent (a fixed number of workgroups strides over the tile
-// table), so the same launch serves any membership.  A tile is a rectangle
-// of one member (whole rows of a narrow lattice, a row segment of a wide
-// one); its cells are walked as a flattened (row, column) index so narrow
-// lattices still fill whole waves.  Member k is active in launch k of
-// a chunk while t_done + k < t_target; its source buffer alternates with
-// t_done + k.  The per-cell work is the same gather9 / cell_update / store9
-// as the single-lattice kernels, so a lattice gives bit-identical results
-// alone or in a pool.
+// A one-step launch advances every active member of one storage class by
+// one step, a T-step launch by T steps.  The grid is persistent (a fixed
+// number of workgroups strides over the tile table), so the same launch
+// serves any membership.  A one-step tile is a rectangle of one member
+// (whole rows of a narrow lattice, a row segment of a wide one) whose cells
+// are walked as a flattened (row, column) index so narrow lattices still
+// fill whole waves; a T-step task is one strip segment of one member, taken
+// by one wave.  Which launches of a recorded chunk a member takes, and hence
+// which of its buffers is the source, follows from its remaining step count
+// (chunk schedule in lbm_internal.hpp).  The per-cell work is the same
+// gather9 / cell_update / store9 and strip_pass as the single-lattice
+// kernels, so a lattice gives bit-identical results alone or in a pool.
 
 template <typename C>
 __device__ __forceinline__ Relax<C> member_relax(const PoolMember *m);
@@ -613,7 +624,7 @@ __device__ __forceinline__ Relax<double> member_relax<double>(const PoolMember *
 
 template <typename S, typename C>
 __global__ void __launch_bounds__(1024) k_pool_step(const PoolHeader *hdr, const PoolMember *mem,
-                                                     const PoolTile *tiles, int cls, int k)
+                                                     const PoolTile *tiles, int cls, int i, int kk, int T)
 {
     using R = typename Store<S>::raw;
     using W = typename Store<S>::wide;
@@ -621,9 +632,11 @@ __global__ void __launch_bounds__(1024) k_pool_step(const PoolHeader *hdr, const
     for (int ti = begin + (int)blockIdx.x; ti < end; ti += (int)gridDim.x) {
         const PoolTile tile = tiles[ti];
         const PoolMember *m = mem + tile.member;
-        const int64_t done = m->t_done;
-        if (done + k >= m->t_target) continue;
-        const int par = (int)((m->cur0 + done + k) & 1);
+        const int64_t rem = m->t_target - m->t_done;
+        const int64_t span = rem < kk ? rem : kk;
+        const int64_t q = member_multi(rem, kk, T);
+        if (i >= span - q * T) continue;                 // not one of its one-step launches
+        const int par = (int)((m->cur0 + m->flips + q + i) & 1);
         const char *__restrict__ src = (const char *)m->buf[par];
         char *__restrict__ dst = (char *)m->buf[par ^ 1];
         const int nx = m->nx, ny = m->ny;
@@ -651,12 +664,36 @@ __global__ void __launch_bounds__(1024) k_pool_step(const PoolHeader *hdr, const
     }
 }
 
-__global__ void k_pool_commit(PoolMember *mem, int nmem, int kk)
+// T-step launch j of a chunk: each wave takes strip tasks of the class in
+// turn; a member takes T-step launches while T more steps fit.
+template <typename S, typename C, int T, int FLAGS>
+__global__ void __launch_bounds__(256) k_pool_multi(const PoolHeader *hdr, const PoolMember *mem,
+                                                    const PoolTile *tiles, int cls, int j)
+{
+    const int begin = hdr->mbegin[cls], end = hdr->mend[cls];
+    const int nw = (int)(gridDim.x * blockDim.y);
+    for (int ti = begin + (int)(blockIdx.x * blockDim.y + threadIdx.y); ti < end; ti += nw) {
+        const PoolTile tile = tiles[ti];                 // wave-uniform
+        const PoolMember *m = mem + tile.member;
+        if ((int64_t)(j + 1) * T > m->t_target - m->t_done) continue;
+        const int par = (int)((m->cur0 + m->flips + j) & 1);
+        strip_pass<S, C, T, FLAGS>((const char *)m->buf[par], (char *)m->buf[par ^ 1], m->nx, m->ny, m->pitch,
+                                   m->plane, member_relax<C>(m), m->scale, m->inv_scale, tile.x0, tile.y0,
+                                   tile.nrows);
+    }
+}
+
+__global__ void k_pool_commit(PoolMember *mem, int nmem, int kk, int T)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nmem) return;
     const int64_t rem = mem[i].t_target - mem[i].t_done;
-    if (rem > 0) mem[i].t_done += rem < kk ? rem : (int64_t)kk;
+    if (rem > 0) {
+        const int64_t span = rem < kk ? rem : (int64_t)kk;
+        const int64_t q = member_multi(rem, kk, T);
+        mem[i].t_done += span;
+        mem[i].flips += q + span - q * T;
+    }
 }
 
 // ---- block reductions (fixed order, deterministic) ---------------------------
@@ -1190,24 +1227,54 @@ void *pool_step_kernel(int cls)
 
 void *pool_commit_kernel() { return reinterpret_cast<void *>(&k_pool_commit); }
 
-hipError_t launch_pool_step(int cls, const PoolHeader *hdr, const PoolMember *mem, const PoolTile *tiles, int k,
-                            int grid, int block, hipStream_t st)
+namespace {
+template <typename S, typename C>
+void *pool_multi_typed(int T, int flags)
 {
-    const dim3 g(grid), b(block);
+#define LBM_PM(T_, F_) \
+    if (T == T_ && flags == F_) return reinterpret_cast<void *>(&k_pool_multi<S, C, T_, F_>);
+#define LBM_PM_T(T_) LBM_PM(T_, 0) LBM_PM(T_, 2) LBM_PM(T_, 4) LBM_PM(T_, 6) LBM_PM(T_, 8) LBM_PM(T_, 12)
+    LBM_PM_T(2)
+    LBM_PM_T(4)
+#undef LBM_PM_T
+#undef LBM_PM
+    return nullptr;
+}
+}  // namespace
+
+void *pool_multi_kernel(int cls, int T, int flags)
+{
     switch (cls) {
-    case LBM_STORE_F64 * 2 + LBM_COMPUTE_F64: hipLaunchKernelGGL((k_pool_step<double, double>), g, b, 0, st, hdr, mem, tiles, cls, k); break;
-    case LBM_STORE_F64 * 2 + LBM_COMPUTE_F32: hipLaunchKernelGGL((k_pool_step<double, float>), g, b, 0, st, hdr, mem, tiles, cls, k); break;
-    case LBM_STORE_F32 * 2 + LBM_COMPUTE_F32: hipLaunchKernelGGL((k_pool_step<float, float>), g, b, 0, st, hdr, mem, tiles, cls, k); break;
-    case LBM_STORE_F16 * 2 + LBM_COMPUTE_F32: hipLaunchKernelGGL((k_pool_step<f16_tag, float>), g, b, 0, st, hdr, mem, tiles, cls, k); break;
-    case LBM_STORE_BF16 * 2 + LBM_COMPUTE_F32: hipLaunchKernelGGL((k_pool_step<bf16_tag, float>), g, b, 0, st, hdr, mem, tiles, cls, k); break;
-    default: return hipErrorInvalidValue;
+    case LBM_STORE_F64 * 2 + LBM_COMPUTE_F64: return pool_multi_typed<double, double>(T, flags);
+    case LBM_STORE_F64 * 2 + LBM_COMPUTE_F32: return pool_multi_typed<double, float>(T, flags);
+    case LBM_STORE_F32 * 2 + LBM_COMPUTE_F32: return pool_multi_typed<float, float>(T, flags);
+    case LBM_STORE_F16 * 2 + LBM_COMPUTE_F32: return pool_multi_typed<f16_tag, float>(T, flags);
+    case LBM_STORE_BF16 * 2 + LBM_COMPUTE_F32: return pool_multi_typed<bf16_tag, float>(T, flags);
+    default: return nullptr;
     }
-    return hipGetLastError();
 }
 
-hipError_t launch_pool_commit(PoolMember *mem, int nmem, int kk, hipStream_t st)
+hipError_t launch_pool_step(int cls, const PoolHeader *hdr, const PoolMember *mem, const PoolTile *tiles, int i,
+                            int kk, int T, int grid, int block, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_pool_commit, dim3((nmem + 255) / 256), dim3(256), 0, st, mem, nmem, kk);
+    void *f = pool_step_kernel(cls);
+    if (!f) return hipErrorInvalidValue;
+    void *args[] = {(void *)&hdr, (void *)&mem, (void *)&tiles, (void *)&cls, (void *)&i, (void *)&kk, (void *)&T};
+    return hipLaunchKernel(f, dim3(grid), dim3(block), args, 0, st);
+}
+
+hipError_t launch_pool_multi(int cls, int T, int flags, const PoolHeader *hdr, const PoolMember *mem,
+                             const PoolTile *tiles, int j, int grid, int waves, hipStream_t st)
+{
+    void *f = pool_multi_kernel(cls, T, flags);
+    if (!f) return hipErrorInvalidValue;
+    void *args[] = {(void *)&hdr, (void *)&mem, (void *)&tiles, (void *)&cls, (void *)&j};
+    return hipLaunchKernel(f, dim3(grid), dim3(64, waves), args, 0, st);
+}
+
+hipError_t launch_pool_commit(PoolMember *mem, int nmem, int kk, int T, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pool_commit, dim3((nmem + 255) / 256), dim3(256), 0, st, mem, nmem, kk, T);
     return hipGetLastError();
 }
 

@@ -43,6 +43,7 @@ size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
 struct Slot {
     lbm_lattice *lat = nullptr;
     int64_t t0 = 0, t_done = 0, t_target = 0;
+    int64_t flips = 0;               // launches taken (buffer swaps) since added
     int cur0 = 0;
     bool finishing = false;          // reached t_target; waiting for poll
     hipEvent_t ev_in = nullptr;      // lattice stream -> pool stream
@@ -73,11 +74,12 @@ struct lbm_pool {
     bool dirty = true;
     unsigned class_mask = 0;         // classes with tiles in the uploaded tables
     int ntiles = 0;
-    int max_class_tiles = 0;         // largest tile range of one class
-    lbm_pool_shape shape{256, 512, 65536, 256};
+    int max_class_tiles = 0;         // largest one-step tile range of one class
+    int max_class_tasks = 0;         // largest T-step task range of one class
+    lbm_pool_shape shape{256, 512, 65536, 256, 4, 32, 4, 2};
     std::vector<Slot> slots;
     std::vector<int> finishing;      // slot indices in completion order
-    std::map<std::tuple<unsigned, int, int>, GraphEntry> graphs;   // (class mask, steps, grid)
+    std::map<std::tuple<unsigned, int, int, int>, GraphEntry> graphs;   // (class mask, steps, grids)
 };
 
 namespace {
@@ -96,10 +98,21 @@ int tile_cols(const lbm_pool_shape &sh, const lbm_lattice *L)
     return L->v.nx <= seg ? L->v.nx : seg;
 }
 
+// T-step strip tasks: 64 - 2(T-1) output columns by seg_rows rows.
+int strip_cols(const lbm_pool_shape &sh) { return 64 - 2 * (sh.steps_per_launch - 1); }
+
+int tasks_of(const lbm_pool_shape &sh, const lbm_lattice *L)
+{
+    if (sh.steps_per_launch < 2) return 0;
+    const int w = strip_cols(sh);
+    return ((L->v.nx + w - 1) / w) * ((L->v.ny + sh.seg_rows - 1) / sh.seg_rows);
+}
+
+// Table entries of one unfinished member: one-step tiles plus T-step tasks.
 int tiles_of(const lbm_pool_shape &sh, const lbm_lattice *L)
 {
     const int r = tile_rows(sh, L), c = tile_cols(sh, L);
-    return ((L->v.ny + r - 1) / r) * ((L->v.nx + c - 1) / c);
+    return ((L->v.ny + r - 1) / r) * ((L->v.nx + c - 1) / c) + tasks_of(sh, L);
 }
 
 void drop_graphs(lbm_pool *P)
@@ -126,7 +139,7 @@ lbm_status upload(lbm_pool *P)
     lbm::PoolTile *tiles = (lbm::PoolTile *)(base + ((char *)P->d_tiles - P->ws));
     memset(base, 0, (size_t)((char *)P->d_tiles - P->ws));
     struct T { int cls; int64_t cells; lbm::PoolTile t; };
-    std::vector<T> all;
+    std::vector<T> all, tasks;
     for (int i = 0; i < P->max_members; ++i) {
         const Slot &s = P->slots[i];
         lbm::PoolMember &m = mem[i];
@@ -144,6 +157,7 @@ lbm_status upload(lbm_pool *P)
         m.plane = L->v.plane;
         m.t_done = s.t_done;
         m.t_target = s.t_target;
+        m.flips = s.flips;
         m.rf = lbm::relax_f32(L->v);
         m.rd = lbm::relax_f64(L->v);
         m.scale = (float)L->v.scale;
@@ -163,14 +177,31 @@ lbm_status upload(lbm_pool *P)
                 t.cells = (int64_t)t.t.nrows * t.t.ncols;
                 all.push_back(t);
             }
+        if (P->shape.steps_per_launch > 1) {
+            const int w = strip_cols(P->shape), sr = P->shape.seg_rows;
+            for (int y0 = 0; y0 < L->v.ny; y0 += sr)
+                for (int x0 = 0; x0 < L->v.nx; x0 += w) {
+                    T t{};
+                    t.cls = m.cls;
+                    t.t.member = i;
+                    t.t.y0 = y0;
+                    t.t.x0 = x0;
+                    t.t.nrows = std::min(sr, L->v.ny - y0);
+                    t.t.ncols = std::min(w, L->v.nx - x0);
+                    t.cells = (int64_t)t.t.nrows * t.t.ncols;
+                    tasks.push_back(t);
+                }
+        }
     }
-    if ((int)all.size() > P->max_tiles) return pfail(LBM_E_NOMEM, "pool needs %zu tiles, has %d", all.size(), P->max_tiles);
-    // group by class, largest tiles first (balances the strided persistent grid)
-    std::stable_sort(all.begin(), all.end(), [](const T &a, const T &b) {
-        return a.cls != b.cls ? a.cls < b.cls : a.cells > b.cells;
-    });
+    if ((int)(all.size() + tasks.size()) > P->max_tiles)
+        return pfail(LBM_E_NOMEM, "pool needs %zu tiles, has %d", all.size() + tasks.size(), P->max_tiles);
+    // group by class, largest first (balances the strided persistent grid);
+    // one-step tiles, then T-step tasks
+    auto order = [](const T &a, const T &b) { return a.cls != b.cls ? a.cls < b.cls : a.cells > b.cells; };
+    std::stable_sort(all.begin(), all.end(), order);
+    std::stable_sort(tasks.begin(), tasks.end(), order);
     unsigned mask = 0;
-    for (int c = 0; c < lbm::kClasses; ++c) hdr->begin[c] = hdr->end[c] = 0;
+    for (int c = 0; c < lbm::kClasses; ++c) hdr->begin[c] = hdr->end[c] = hdr->mbegin[c] = hdr->mend[c] = 0;
     for (size_t j = 0; j < all.size(); ++j) {
         tiles[j] = all[j].t;
         const int c = all[j].cls;
@@ -178,10 +209,22 @@ lbm_status upload(lbm_pool *P)
         hdr->end[c] = (int)j + 1;
         mask |= 1u << c;
     }
-    P->ntiles = (int)all.size();
-    P->max_class_tiles = 0;
-    for (int c = 0; c < lbm::kClasses; ++c) P->max_class_tiles = std::max(P->max_class_tiles, hdr->end[c] - hdr->begin[c]);
-    const size_t used = (size_t)((char *)P->d_tiles - P->ws) + sizeof(lbm::PoolTile) * all.size();
+    unsigned tmask = 0;
+    for (size_t j = 0; j < tasks.size(); ++j) {
+        const int at = (int)(all.size() + j);
+        tiles[at] = tasks[j].t;
+        const int c = tasks[j].cls;
+        if (!(tmask & (1u << c))) hdr->mbegin[c] = at;
+        hdr->mend[c] = at + 1;
+        tmask |= 1u << c;
+    }
+    P->ntiles = (int)(all.size() + tasks.size());
+    P->max_class_tiles = P->max_class_tasks = 0;
+    for (int c = 0; c < lbm::kClasses; ++c) {
+        P->max_class_tiles = std::max(P->max_class_tiles, hdr->end[c] - hdr->begin[c]);
+        P->max_class_tasks = std::max(P->max_class_tasks, hdr->mend[c] - hdr->mbegin[c]);
+    }
+    const size_t used = (size_t)((char *)P->d_tiles - P->ws) + sizeof(lbm::PoolTile) * (size_t)P->ntiles;
     if ((e = hipMemcpyAsync(P->ws, P->stage, used, hipMemcpyHostToDevice, P->stream)) != hipSuccess)
         return phip(e, "hipMemcpyAsync (pool tables)");
     if ((e = hipEventRecord(P->ev_stage, P->stream)) != hipSuccess) return phip(e, "hipEventRecord");
@@ -200,12 +243,25 @@ int launch_grid(const lbm_pool *P)
     return std::min(g, P->shape.grid);
 }
 
-// Records a step loop of `len` steps (one launch per class in `mask` and
-// step, each step depending on the previous one), then the commit kernel.
+// Workgroups of a T-step launch: enough waves for the largest class's
+// tasks, rounded up to a power of two, at most the shape's grid.
+int multi_grid(const lbm_pool *P)
+{
+    const int need = (P->max_class_tasks + P->shape.waves - 1) / P->shape.waves;
+    int g = 1;
+    while (g < need && g < P->shape.grid) g *= 2;
+    return std::min(g, P->shape.grid);
+}
+
+// Records a step loop of `len` steps: the chunk schedule of
+// lbm_internal.hpp (len / T T-step launches, then the one-step launches,
+// one node per class in `mask`, each depending on the previous launch),
+// then the commit kernel.
 lbm_status get_graph(lbm_pool *P, unsigned mask, int len, hipGraphExec_t *out)
 {
-    const int grid = launch_grid(P);
-    auto key = std::make_tuple(mask, len, grid);
+    const int grid = launch_grid(P), mgrid = multi_grid(P);
+    const int T = P->shape.steps_per_launch;
+    auto key = std::make_tuple(mask, len, grid, mgrid);
     auto it = P->graphs.find(key);
     if (it != P->graphs.end()) {
         *out = it->second.exec;
@@ -218,32 +274,37 @@ lbm_status get_graph(lbm_pool *P, unsigned mask, int len, hipGraphExec_t *out)
     const lbm::PoolHeader *hdr = P->d_hdr;
     const lbm::PoolMember *mem = P->d_mem;
     const lbm::PoolTile *tiles = P->d_tiles;
-    for (int k = 0; k < len; ++k) {
+    const int nmulti = lbm::chunk_multi_launches(len, T), nsingle = lbm::chunk_single_launches(len, T);
+    for (int k = 0; k < nmulti + nsingle; ++k) {
         cur.clear();
+        const bool multi = k < nmulti;
         for (int c = 0; c < lbm::kClasses; ++c) {
             if (!(mask & (1u << c))) continue;
-            int cls = c, kk = k;
-            void *args[] = {(void *)&hdr, (void *)&mem, (void *)&tiles, (void *)&cls, (void *)&kk};
+            int cls = c, idx = multi ? k : k - nmulti, kk = len, TT = T;
+            void *margs[] = {(void *)&hdr, (void *)&mem, (void *)&tiles, (void *)&cls, (void *)&idx};
+            void *sargs[] = {(void *)&hdr, (void *)&mem, (void *)&tiles, (void *)&cls, (void *)&idx, (void *)&kk,
+                             (void *)&TT};
             hipKernelNodeParams np{};
-            np.func = lbm::pool_step_kernel(c);
-            np.gridDim = dim3(grid);
-            np.blockDim = dim3(P->shape.block);
+            np.func = multi ? lbm::pool_multi_kernel(c, T, P->shape.flags) : lbm::pool_step_kernel(c);
+            np.gridDim = dim3(multi ? mgrid : grid);
+            np.blockDim = multi ? dim3(64, P->shape.waves) : dim3(P->shape.block);
             np.sharedMemBytes = 0;
-            np.kernelParams = args;
+            np.kernelParams = multi ? margs : sargs;
             np.extra = nullptr;
             hipGraphNode_t n;
-            if ((e = hipGraphAddKernelNode(&n, g.graph, prev.empty() ? nullptr : prev.data(), prev.size(), &np)) !=
-                hipSuccess) {
+            if (!np.func ||
+                (e = hipGraphAddKernelNode(&n, g.graph, prev.empty() ? nullptr : prev.data(), prev.size(), &np)) !=
+                    hipSuccess) {
                 (void)hipGraphDestroy(g.graph);
-                return phip(e, "hipGraphAddKernelNode");
+                return np.func ? phip(e, "hipGraphAddKernelNode") : pfail(LBM_E_INVAL, "no pool kernel for this shape");
             }
             cur.push_back(n);
         }
         prev.swap(cur);
     }
     lbm::PoolMember *memw = P->d_mem;
-    int nmem = P->max_members, kk = len;
-    void *cargs[] = {(void *)&memw, (void *)&nmem, (void *)&kk};
+    int nmem = P->max_members, kk = len, TT = T;
+    void *cargs[] = {(void *)&memw, (void *)&nmem, (void *)&kk, (void *)&TT};
     hipKernelNodeParams cp{};
     cp.func = lbm::pool_commit_kernel();
     cp.gridDim = dim3((nmem + 255) / 256);
@@ -277,7 +338,10 @@ lbm_status run_chunk(lbm_pool *P, int kk)
         Slot &s = P->slots[i];
         if (!s.lat || s.finishing) continue;
         const int64_t rem = s.t_target - s.t_done;
-        s.t_done += std::min<int64_t>(rem, kk);
+        const int64_t span = std::min<int64_t>(rem, kk);
+        const int64_t q = lbm::member_multi(rem, kk, P->shape.steps_per_launch);
+        s.t_done += span;
+        s.flips += q + span - q * P->shape.steps_per_launch;
         if (s.t_done >= s.t_target) {
             s.finishing = true;
             if ((e = hipEventRecord(s.ev_done, P->stream)) != hipSuccess) return phip(e, "hipEventRecord");
@@ -289,8 +353,12 @@ lbm_status run_chunk(lbm_pool *P, int kk)
 
 bool valid_shape(const lbm_pool_shape &s)
 {
+    const bool multi_ok = s.steps_per_launch == 1 ||
+                          ((s.steps_per_launch == 2 || s.steps_per_launch == 4) && s.seg_rows >= 1 &&
+                           s.seg_rows <= 4096 && s.waves >= 1 && s.waves <= 4 &&
+                           lbm::pool_multi_kernel(LBM_STORE_F32 * 2 + LBM_COMPUTE_F32, s.steps_per_launch, s.flags));
     return s.tile_cells >= 64 && s.tile_cells <= (1 << 22) && s.block >= 64 && s.block <= 1024 && s.block % 64 == 0 &&
-           s.grid >= 1 && s.grid <= (1 << 20) && s.graph_steps >= 1 && s.graph_steps <= 1024;
+           s.grid >= 1 && s.grid <= (1 << 20) && s.graph_steps >= 1 && s.graph_steps <= 1024 && multi_ok;
 }
 
 // Hands a member back to its lattice: host state and stream order.
@@ -304,11 +372,11 @@ lbm_status release(lbm_pool *P, int i)
     }
     if ((e = hipStreamWaitEvent(L->stream, s.ev_done, 0)) != hipSuccess) return phip(e, "hipStreamWaitEvent");
     L->t = s.t0 + s.t_done;
-    L->cur = (int)((s.cur0 + s.t_done) & 1);
+    L->cur = (int)((s.cur0 + s.flips) & 1);
     L->pool = nullptr;
     s.lat = nullptr;
     s.finishing = false;
-    s.t_done = s.t_target = 0;
+    s.t_done = s.t_target = s.flips = 0;
     P->dirty = true;
     return LBM_OK;
 }
@@ -407,6 +475,7 @@ lbm_status lbm_pool_add(lbm_pool *pool, lbm_lattice *lat, int64_t nsteps)
     s.t0 = lat->t;
     s.cur0 = lat->cur;
     s.t_done = 0;
+    s.flips = 0;
     s.t_target = nsteps;
     s.finishing = false;
     lat->pool = pool;
@@ -538,13 +607,18 @@ lbm_status lbm_pool_time_launches(lbm_pool *pool, int32_t reps, double *avg_us)
         (void)hipEventDestroy(e0);
         return phip(e, "hipEventCreate");
     }
-    // k = 0 without commit: every active member recomputes its next state
-    // into its other buffer; the state itself does not change.
+    // The first launch of a chunk without commit: every active member
+    // recomputes its next state into its other buffer; the state itself
+    // does not change.
+    const int T = pool->shape.steps_per_launch;
     auto launch_all = [&]() -> hipError_t {
         for (int c = 0; c < lbm::kClasses; ++c) {
             if (!(pool->class_mask & (1u << c))) continue;
-            hipError_t r = lbm::launch_pool_step(c, pool->d_hdr, pool->d_mem, pool->d_tiles, 0, launch_grid(pool),
-                                                 pool->shape.block, pool->stream);
+            hipError_t r = T > 1 ? lbm::launch_pool_multi(c, T, pool->shape.flags, pool->d_hdr, pool->d_mem,
+                                                          pool->d_tiles, 0, multi_grid(pool), pool->shape.waves,
+                                                          pool->stream)
+                                 : lbm::launch_pool_step(c, pool->d_hdr, pool->d_mem, pool->d_tiles, 0, 1, 1,
+                                                         launch_grid(pool), pool->shape.block, pool->stream);
             if (r != hipSuccess) return r;
         }
         return hipSuccess;
@@ -569,22 +643,53 @@ lbm_status lbm_pool_tune(lbm_pool *pool, int32_t reps, lbm_pool_shape *best, dou
     const lbm_pool_shape keep = pool->shape;
     lbm_pool_shape best_s = keep;
     double best_t = INFINITY;
+    auto consider = [&](const lbm_pool_shape &s) -> lbm_status {
+        if (lbm_pool_set_shape(pool, &s) != LBM_OK) return LBM_OK;   // does not fit: skip
+        double us;
+        lbm_status st = lbm_pool_time_launches(pool, reps, &us);
+        if (st != LBM_OK) return st;
+        us /= s.steps_per_launch;                                      // per step
+        if (us < best_t) {
+            best_t = us;
+            best_s = s;
+        }
+        return LBM_OK;
+    };
+    // one step per launch: tile, workgroup and grid sizes
+    lbm_pool_shape single = keep;
+    single.steps_per_launch = 1;
+    double single_t = INFINITY;
     for (int cells : {256, 512, 1024, 2048, 4096, 16384})
         for (int block : {256, 512, 1024})
             for (int grid : {1024, 4096, 16384, 65536, 262144}) {
                 lbm_pool_shape s = keep;
+                s.steps_per_launch = 1;
                 s.tile_cells = cells;
                 s.block = block;
                 s.grid = grid;
-                if (lbm_pool_set_shape(pool, &s) != LBM_OK) continue;
-                double us;
-                lbm_status st = lbm_pool_time_launches(pool, reps, &us);
+                const double before = best_t;
+                lbm_status st = consider(s);
                 if (st != LBM_OK) return st;
-                if (us < best_t) {
-                    best_t = us;
-                    best_s = s;
+                if (best_t < before && best_t < single_t) {
+                    single_t = best_t;
+                    single = s;
                 }
             }
+    // several steps per launch (their left-over steps use the best one-step tiles)
+    for (int T : {2, 4})
+        for (int seg : {32, 64, 128})
+            for (int waves : {1, 2, 4})
+                for (int flags : {0, 2, 4, 12})
+                    for (int grid : {4096, 16384, 65536}) {
+                        lbm_pool_shape s = single;
+                        s.steps_per_launch = T;
+                        s.seg_rows = seg;
+                        s.waves = waves;
+                        s.flags = flags;
+                        s.grid = grid;
+                        lbm_status st = consider(s);
+                        if (st != LBM_OK) return st;
+                    }
     lbm_status st = lbm_pool_set_shape(pool, &best_s);
     if (st != LBM_OK) return st;
     if (best) *best = best_s;

@@ -61,13 +61,21 @@ class Pool:
     def shape(self):
         return _lib.lbm_pool_get_shape(self._h).as_dict()
 
-    def set_shape(self, tile_cells=256, block=512, grid=65536, graph_steps=256):
-        _lib.lbm_pool_set_shape(self._h, _lib.lbm_pool_shape(tile_cells, block, grid, graph_steps))
+    def set_shape(self, tile_cells=256, block=512, grid=65536, graph_steps=256, steps_per_launch=4, seg_rows=32,
+                  waves=4, flags=2):
+        """steps_per_launch 1 advances every member one step per launch over
+        tiles of about tile_cells cells; 2 or 4 uses strip tasks of the
+        several-steps-per-pass kernel (seg_rows rows, `waves` waves per
+        workgroup, kernel flags as for Lattice.set_launch)."""
+        _lib.lbm_pool_set_shape(self._h, _lib.lbm_pool_shape(tile_cells, block, grid, graph_steps, steps_per_launch,
+                                                             seg_rows, waves, flags))
         return self
 
     def time_launches(self, reps=5):
+        """Microseconds per launch (steps_per_launch steps of every member)."""
         return _lib.lbm_pool_time_launches(self._h, reps)
 
     def tune(self, reps=5):
+        """Selects the shape with the least time per step; returns (shape, us per step)."""
         s, us = _lib.lbm_pool_tune(self._h, reps)
         return s.as_dict(), us

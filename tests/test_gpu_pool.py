@@ -35,12 +35,19 @@ SETS = [[1.64, 1.54, 1.9, 1.98], [1.3, 1.1, 1.7, 1.85], [1.99, 1.962820428, 1.99
 SIZES = [(64, 64), (100, 37), (257, 64), (33, 190), (1, 9), (128, 128)]
 STORES = ["f32", "f16", "f64", "bf16", "f32", "f32"]
 STEPS = [37, 100, 0, 64, 5, 91]
+# one step per launch, and T-step strip tasks (T = 2, 4) with their one-step
+# launches for left-over steps; recorded loops of 16 / 8 / 10 steps give
+# chunks shorter than T as well
+SCHEDULES = [dict(steps_per_launch=1), dict(steps_per_launch=2, seg_rows=16, waves=2, flags=0),
+             dict(steps_per_launch=4, seg_rows=32, waves=4, flags=2),
+             dict(steps_per_launch=4, seg_rows=7, waves=1, flags=12)]
 
 
-def test_members_match_alone_bitwise_with_own_step_counts():
+@pytest.mark.parametrize("sched", SCHEDULES)
+def test_members_match_alone_bitwise_with_own_step_counts(sched):
     from paper_1107_4543_amd.pool import Pool
     pool = Pool(max_members=16, max_tiles=4096)
-    pool.set_shape(tile_cells=512, block=256, grid=64, graph_steps=16)
+    pool.set_shape(tile_cells=512, block=256, grid=64, graph_steps=16, **sched)
     lats, twins = [], []
     for i, ((nx, ny), s, st, n) in enumerate(zip(SIZES, SETS, STORES, STEPS)):
         lat, f = make(nx, ny, s, st, seed=i, u0=(0.02 * (i % 2), 0.0))
@@ -64,11 +71,12 @@ def test_members_match_alone_bitwise_with_own_step_counts():
     pool.close()
 
 
-def test_continuous_membership_and_remove():
+@pytest.mark.parametrize("sched", SCHEDULES)
+def test_continuous_membership_and_remove(sched):
     from paper_1107_4543_amd import _lib
     from paper_1107_4543_amd.pool import Pool
     pool = Pool(max_members=4, max_tiles=1024)
-    pool.set_shape(tile_cells=1024, block=128, grid=32, graph_steps=8)
+    pool.set_shape(tile_cells=1024, block=128, grid=32, graph_steps=8, **sched)
     s = SETS[0]
     a, fa = make(96, 40, s, "f32", seed=1)
     b, fb = make(50, 70, s, "f32", seed=2)
@@ -100,10 +108,11 @@ def test_continuous_membership_and_remove():
     pool.close()
 
 
-def test_pool_member_parity_with_oracle_fp64():
+@pytest.mark.parametrize("sched", SCHEDULES)
+def test_pool_member_parity_with_oracle_fp64(sched):
     from paper_1107_4543_amd.pool import Pool
     pool = Pool(max_members=4, max_tiles=512)
-    pool.set_shape(tile_cells=256, block=64, grid=16, graph_steps=10)
+    pool.set_shape(tile_cells=256, block=64, grid=16, graph_steps=10, **sched)
     s = [1.64, 1.54, 1.9, float(linear.s_from_nu(1e-3))]
     lat, (rho, ux, uy) = make(48, 30, s, "f64", seed=7, u0=(0.03, 0.0))
     pool.add(lat, 77)
