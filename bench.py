@@ -184,7 +184,15 @@ def bench_batch256(args):
     init_all()
     for lat in lats:
         pool.add(lat, steps)
-    shape, _ = pool.tune(reps=3)
+    if args.pool_shape:
+        keys = ["tile_cells", "block", "grid", "graph_steps", "steps_per_launch", "seg_rows", "waves", "flags"]
+        vals = [int(v) for v in args.pool_shape.split(",")]
+        if len(vals) != len(keys):
+            raise SystemExit("--pool-shape takes " + ",".join(keys))
+        pool.set_shape(**dict(zip(keys, vals)))
+        shape = pool.shape
+    else:
+        shape, _ = pool.tune(reps=3)
     pool.step(steps)                                  # untimed warm-up pass (records the graph)
     while pool.members:
         pool.poll(wait=True)
@@ -360,11 +368,14 @@ def main():
     ap.add_argument("--rates", default="10,30,100,300,1000", help="serve: arrival rates (jobs/s)")
     ap.add_argument("--jobs", type=int, default=40, help="serve: jobs per rate")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget for admitted jobs")
-    ap.add_argument("--no-tune", action="store_true", help="use the library's default one-step launch shape")
+    ap.add_argument("--no-tune", action="store_true", help="use the library's default launch shape (four steps per launch from 2^22 cells)")
     ap.add_argument("--tune", action="store_true", help="search the launch shape with lbm_tune before timing")
     ap.add_argument("--launch", default=None,
                     help="launch shape variant,block_x,block_y,rows,xcd_remap,flags (default: the recorded "
                          "tuned shape for the storage type)")
+    ap.add_argument("--pool-shape", default=None,
+                    help="batch256: pool shape tile_cells,block,grid,graph_steps,steps_per_launch,seg_rows,waves,"
+                         "flags (no tuning)")
     ap.add_argument("--probe", choices=["copy"], default=None,
                     help="run only the device-to-device copy probe")
     ap.add_argument("--probe-bytes", type=int, default=1 << 30)

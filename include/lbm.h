@@ -100,7 +100,9 @@ typedef struct lbm_desc {
 
 typedef struct lbm_lattice lbm_lattice;
 
-/* Launch shape of the fused step kernel (chosen by lbm_tune or set by hand).
+/* Launch shape of the fused step kernel (chosen by lbm_tune or set by hand;
+ * a new lattice of at least 2^22 cells starts with {10, 64, 4, 32, 1, 2},
+ * four steps per launch, a smaller one with {0, 64, 4, 1, 1, 0}).
  *   variant   0 = one cell per lane (nine direct loads),
  *             1, 2, 3 = 2, 4, 8 consecutive cells per lane (aligned vector
  *             loads, x-shift by cross-lane exchange; needs nx % 2^variant == 0
