@@ -129,7 +129,10 @@ typedef struct lbm_lattice lbm_lattice;
  *             (variants 8, 9, 10 only): move values between neighbouring
  *             lanes with DPP whole-wave shifts instead of LDS shuffles; bit 3
  *             (variants 8, 9, 10 only, not with bit 1): issue the loads two
- *             rows ahead.
+ *             rows ahead; bit 4 (variants 9 and 10 only, not with bit 0):
+ *             skewed pipeline, in which stage p works two rows behind stage
+ *             p-1 instead of one, so that the T collisions of a row
+ *             iteration do not depend on each other.
  * Every shape produces bit-identical results. */
 typedef struct lbm_launch {
     int32_t variant;

@@ -161,8 +161,8 @@ std::vector<lbm_launch> multi_candidates(const View &v)
     std::vector<lbm_launch> out;
     for (int var = 8; var <= 10; ++var)
         for (int by : {1, 2, 4})
-            for (int rows : {32, 64, 128, 256})
-                for (int flags : {0, 2, 4, 6, 8, 12}) {
+            for (int rows : {32, 64, 128, 176, 256})
+                for (int flags : {0, 2, 4, 6, 8, 12, 16, 18, 20, 28}) {
                     lbm_launch c{};
                     c.variant = var;
                     c.block_x = 64;

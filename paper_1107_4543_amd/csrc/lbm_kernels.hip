@@ -483,6 +483,10 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
     constexpr bool DPP = (FLAGS & 4) != 0;
     // rows of stage-0 loads issued ahead of the row being collided
     constexpr int AHEAD = (FLAGS & 8) ? 2 : ((FLAGS & 2) ? 1 : 0);
+    // skewed pipeline: stage p works on row r - 2p and reads only outputs of
+    // earlier iterations, so the T collides of an iteration are independent
+    constexpr bool SKEW = (FLAGS & 16) != 0;
+    constexpr int LAG = SKEW ? 3 : 2;                   // iterations from one stage's start to the next
     constexpr uint32_t E = sizeof(R);
     const int lane = threadIdx.x;
     const int xl = x0 + lane - (T - 1);                 // unwrapped column
@@ -493,7 +497,7 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
     const bool writes = lane >= T - 1 && lane <= 64 - T && xl < nx;
     const uint64_t pb = (uint64_t)plane * E;
     const uint32_t rb = (uint32_t)pitch * E;
-    const int iters = len + 2 * (T - 1);
+    const int iters = len + LAG * (T - 1);
     auto gather = [&](int r, W w[9]) {
         const int y = wrap_mod(r, ny);
         const int ym = (y == 0 ? ny : y) - 1;
@@ -503,6 +507,18 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
     // outputs of stage p kept for stage p + 1: populations 2, 5, 6 of the row
     // before the last one produced, and 0, 1, 3, 2, 5, 6 of the last one
     W up[T > 1 ? T - 1 : 1][3], mid[T > 1 ? T - 1 : 1][6];
+    // skewed pipeline: stage p-1's outputs of the last three iterations
+    // (all nine; 0, 1, 3, 2, 5, 6; 2, 5, 6)
+    W r1[T > 1 ? T - 1 : 1][9], r2[T > 1 ? T - 1 : 1][6], r3[T > 1 ? T - 1 : 1][3];
+#pragma unroll
+    for (int p = 0; p < (T > 1 ? T - 1 : 1); ++p) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) up[p][i] = r3[p][i] = W(0);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) mid[p][i] = r2[p][i] = W(0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) r1[p][i] = W(0);
+    }
     W ahead[AHEAD > 0 ? AHEAD : 1][9];
     const int r_first = y0 - (T - 1);
 #pragma unroll
@@ -563,27 +579,87 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
             if (p == T - 1 && writes) store9<S>(dst, pb, (uint32_t)(r - (T - 1)) * rb + c0, w);
         }
     };
+    // The skewed pipeline's row: every stage reads only registers filled in
+    // earlier iterations; the boundaries rotate after all stages have run.
+    // Stage p starts at iteration 3p; its row is r - 2p.
+    auto row_skew = [&](int j, auto steady, W(&slot)[9]) {
+        constexpr bool STEADY = decltype(steady)::value;
+        const int r = r_first + j;                      // row of stage 0
+        W w[9];
+        if constexpr (AHEAD > 0) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) w[i] = slot[i];
+            gather(r + AHEAD, slot);
+        } else {
+            gather(r, w);
+        }
+        cell_update<S, C>(w, relax, scale, inv_scale);
+        W res[T > 1 ? T - 1 : 1][9];
+#pragma unroll
+        for (int p = 1; p < T; ++p) {
+            const bool active = STEADY || j >= 3 * p;   // wave-uniform
+            W in[9];
+            if (active) {
+                in[0] = r2[p - 1][0];
+                in[1] = from_left<DPP>(r2[p - 1][1]);
+                in[3] = from_right<DPP>(r2[p - 1][2]);
+                in[2] = r3[p - 1][0];
+                in[5] = from_left<DPP>(r3[p - 1][1]);
+                in[6] = from_right<DPP>(r3[p - 1][2]);
+                in[4] = r1[p - 1][4];
+                in[7] = from_right<DPP>(r1[p - 1][7]);
+                in[8] = from_left<DPP>(r1[p - 1][8]);
+                cell_update<S, C>(in, relax, scale, inv_scale);
+                if (p == T - 1 && writes) store9<S>(dst, pb, (uint32_t)(r - 2 * (T - 1)) * rb + c0, in);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) in[i] = W(0);
+            }
+#pragma unroll
+            for (int i = 0; i < 9; ++i) res[p - 1][i] = in[i];
+        }
+#pragma unroll
+        for (int p = 1; p < T; ++p) {
+            r3[p - 1][0] = r2[p - 1][3];
+            r3[p - 1][1] = r2[p - 1][4];
+            r3[p - 1][2] = r2[p - 1][5];
+            r2[p - 1][0] = r1[p - 1][0];
+            r2[p - 1][1] = r1[p - 1][1];
+            r2[p - 1][2] = r1[p - 1][3];
+            r2[p - 1][3] = r1[p - 1][2];
+            r2[p - 1][4] = r1[p - 1][5];
+            r2[p - 1][5] = r1[p - 1][6];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) r1[p - 1][i] = round_trip<S>(p == 1 ? w[i] : res[p - 2][i]);
+        }
+    };
     // Two rows per trip (the compiler does not unroll loops that hold
     // cross-lane operations by a runtime count itself); the even row of a
     // trip uses slot 0, the odd one slot AHEAD - 1.  The prologue has an even
     // number of rows unless the whole segment is shorter.
     constexpr int S1 = AHEAD > 1 ? 1 : 0;
-    const int pro = min(iters, 2 * (T - 1));
+    auto step_row = [&](int jj, auto steady, W(&slot)[9]) {
+        if constexpr (SKEW) row_skew(jj, steady, slot);
+        else row(jj, steady, slot);
+    };
+    // prologue rounded up to an even number of rows (the skewed one has
+    // 3(T-1) rows of start-up, odd for T = 2 and 4)
+    const int pro = min(iters, (LAG * (T - 1) + 1) & ~1);
     int j = 0;
     for (; j + 1 < pro; j += 2) {
-        row(j, std::false_type{}, ahead[0]);
-        row(j + 1, std::false_type{}, ahead[S1]);
+        step_row(j, std::false_type{}, ahead[0]);
+        step_row(j + 1, std::false_type{}, ahead[S1]);
     }
     if (j < pro) {
         // odd prologue: the segment ends inside it (j + 1 == pro == iters)
-        row(j, std::false_type{}, ahead[0]);
+        step_row(j, std::false_type{}, ahead[0]);
         ++j;
     }
     for (; j + 1 < iters; j += 2) {
-        row(j, std::true_type{}, ahead[0]);
-        row(j + 1, std::true_type{}, ahead[S1]);
+        step_row(j, std::true_type{}, ahead[0]);
+        step_row(j + 1, std::true_type{}, ahead[S1]);
     }
-    if (j < iters) row(j, std::true_type{}, ahead[0]);
+    if (j < iters) step_row(j, std::true_type{}, ahead[0]);
 }
 
 template <typename S, typename C, int T, int FLAGS>
@@ -1005,15 +1081,18 @@ hipError_t launch_step_typed(const View &v, const void *src, void *dst, const lb
     }
     const dim3 grid(a.nblocks), block(cfg.block_x, cfg.block_y);
     if (cfg.variant >= 8) {
-        switch ((cfg.variant - 8) * 16 + cfg.flags) {
+        switch ((cfg.variant - 8) * 32 + cfg.flags) {
 #define LBM_MULTI(T_, F_)                                                                    \
-    case (T_ - 2) * 16 + F_: hipLaunchKernelGGL((k_step_multi<S, C, T_, F_>), grid, block, 0, st, a); break;
+    case (T_ - 2) * 32 + F_: hipLaunchKernelGGL((k_step_multi<S, C, T_, F_>), grid, block, 0, st, a); break;
 #define LBM_MULTI_T(T_) LBM_MULTI(T_, 0) LBM_MULTI(T_, 1) LBM_MULTI(T_, 2) LBM_MULTI(T_, 3) \
                         LBM_MULTI(T_, 4) LBM_MULTI(T_, 5) LBM_MULTI(T_, 6) LBM_MULTI(T_, 7) \
                         LBM_MULTI(T_, 8) LBM_MULTI(T_, 9) LBM_MULTI(T_, 12) LBM_MULTI(T_, 13)
         LBM_MULTI_T(2)
         LBM_MULTI_T(3)
         LBM_MULTI_T(4)
+        // skewed pipeline (bit 4), T = 3 and 4
+        LBM_MULTI(3, 16) LBM_MULTI(3, 18) LBM_MULTI(3, 20) LBM_MULTI(3, 22) LBM_MULTI(3, 24) LBM_MULTI(3, 28)
+        LBM_MULTI(4, 16) LBM_MULTI(4, 18) LBM_MULTI(4, 20) LBM_MULTI(4, 22) LBM_MULTI(4, 24) LBM_MULTI(4, 28)
 #undef LBM_MULTI_T
 #undef LBM_MULTI
         default: return hipErrorInvalidValue;
@@ -1146,7 +1225,9 @@ bool step_shape_supported(const View &v, const lbm_launch &cfg)
         // several steps per pass: one wave per strip and segment
         return cfg.block_x == 64 && cfg.block_y >= 1 && cfg.block_y <= 4 && cfg.rows >= 1 &&
                cfg.rows <= 4096 && (cfg.xcd_remap == 0 || cfg.xcd_remap == 1) && cfg.flags >= 0 &&
-               cfg.flags <= 13 && !((cfg.flags & 8) && (cfg.flags & 2));
+               cfg.flags <= 29 && !((cfg.flags & 8) && (cfg.flags & 2)) &&
+               // skewed pipeline: T = 3 and 4, no non-temporal loads
+               (!(cfg.flags & 16) || (cfg.variant >= 9 && !(cfg.flags & 1)));
     }
     if (cfg.variant < 0 || cfg.variant > 7) return false;
     if (cfg.block_x < 1 || cfg.block_y < 1 || cfg.rows < 1 || cfg.rows > 64) return false;

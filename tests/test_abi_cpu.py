@@ -145,6 +145,7 @@ def test_multi_step_shapes_are_validated_and_report_their_steps():
     try:
         for variant, steps in [(0, 1), (4, 1), (7, 1), (8, 2), (9, 3), (10, 4)]:
             assert _lib.lbm_steps_per_launch(_lib.lbm_launch(variant, 64, 1, 16, 1, 0)) == steps
+        _lib.lbm_set_launch(h, _lib.lbm_launch(10, 64, 2, 64, 1, 28))
         _lib.lbm_set_launch(h, _lib.lbm_launch(9, 64, 4, 4096, 0, 7))
         assert _lib.lbm_get_launch(h).variant == 9
         for bad in [(8, 128, 1, 16, 1, 0),      # one wave along x
@@ -152,7 +153,9 @@ def test_multi_step_shapes_are_validated_and_report_their_steps():
                     (8, 64, 1, 0, 1, 0),        # rows >= 1
                     (10, 64, 1, 4097, 1, 0),    # rows <= 4096
                     (9, 64, 1, 16, 2, 0),       # xcd_remap 0 or 1
-                    (10, 64, 1, 16, 1, 14),     # flags 0..13
+                    (10, 64, 1, 16, 1, 30),     # flags 0..29
+                    (8, 64, 1, 16, 1, 16),      # skewed pipeline needs T >= 3
+                    (10, 64, 1, 16, 1, 17),     # not with non-temporal loads
                     (10, 64, 1, 16, 1, 10),     # one and two rows ahead together
                     (4, 64, 1, 1, 1, 4),        # bit 2 only for several steps per launch
                     (11, 64, 1, 16, 1, 0)]:     # no such variant

@@ -95,7 +95,11 @@ def test_all_launch_shapes_give_identical_results(storage):
                    dict(variant=9, block_x=64, block_y=4, rows=5, xcd_remap=0, flags=7),
                    dict(variant=10, block_x=64, block_y=1, rows=128, xcd_remap=1, flags=6),
                    dict(variant=10, block_x=64, block_y=2, rows=9, xcd_remap=1, flags=12),
-                   dict(variant=8, block_x=64, block_y=4, rows=1, xcd_remap=0, flags=13)]:
+                   dict(variant=8, block_x=64, block_y=4, rows=1, xcd_remap=0, flags=13),
+                   # skewed pipeline
+                   dict(variant=10, block_x=64, block_y=1, rows=256, xcd_remap=1, flags=18),
+                   dict(variant=9, block_x=64, block_y=3, rows=5, xcd_remap=0, flags=28),
+                   dict(variant=10, block_x=64, block_y=4, rows=1, xcd_remap=1, flags=20)]:
         lat = lattice(nx, ny, s, storage, u0=(0.02, 0.01))
         lat.set_launch(**launch)
         f = lat.init(rho, ux, uy).step(25).populations()
@@ -115,7 +119,8 @@ def test_several_steps_per_launch_equal_single_steps(storage, nx, ny):
     kw = dict(u0=(0.02, -0.01), scale_exp=22 if storage in ("f16", "bf16") else None)
     ref = lattice(nx, ny, s, storage, **kw).init(rho, ux, uy).step(7).populations()
     for variant, rows, flags in [(8, 4, 0), (9, 1, 3), (10, 64, 2), (8, 3, 4), (9, 16, 5), (10, 2, 6),
-                                 (10, 1, 12), (9, 5, 9), (8, 64, 13)]:
+                                 (10, 1, 12), (9, 5, 9), (8, 64, 13), (10, 3, 16), (9, 64, 18), (10, 2, 22),
+                                 (10, 7, 24), (9, 1, 28)]:
         lat = lattice(nx, ny, s, storage, **kw)
         lat.set_launch(variant=variant, block_x=64, block_y=2, rows=rows, xcd_remap=1, flags=flags)
         assert lat.steps_per_launch == variant - 6
