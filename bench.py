@@ -83,9 +83,9 @@ def read_traffic(workload, storage, launch):
 
 
 # Launch shapes lbm_tune selected for the 4096^2 wave workload on MI355X
-# (variant 10: four steps per pass); --tune searches again.
-DEFAULT_LAUNCH = {"f32": "10,64,1,256,1,2", "f16": "10,64,4,32,1,2", "bf16": "10,64,4,32,1,6",
-                  "f64": "10,64,4,32,1,12"}
+# (variants 11 and 12: five and six steps per pass); --tune searches again.
+DEFAULT_LAUNCH = {"f32": "12,64,4,176,1,2", "f16": "11,64,1,64,1,0", "bf16": "11,64,1,64,1,2",
+                  "f64": "12,64,1,176,1,12"}
 
 
 def build_waves4096(storage):

@@ -101,8 +101,8 @@ typedef struct lbm_desc {
 typedef struct lbm_lattice lbm_lattice;
 
 /* Launch shape of the fused step kernel (chosen by lbm_tune or set by hand;
- * a new lattice of at least 2^22 cells starts with {10, 64, 4, 32, 1, 2},
- * four steps per launch, a smaller one with {0, 64, 4, 1, 1, 0}).
+ * a new lattice of at least 2^22 cells starts with {11, 64, 4, 64, 1, 2},
+ * five steps per launch, a smaller one with {0, 64, 4, 1, 1, 0}).
  *   variant   0 = one cell per lane (nine direct loads),
  *             1, 2, 3 = 2, 4, 8 consecutive cells per lane (aligned vector
  *             loads, x-shift by cross-lane exchange; needs nx % 2^variant == 0
@@ -112,9 +112,11 @@ typedef struct lbm_lattice lbm_lattice;
  *             5, 6, 7 = 2, 4, 8 consecutive cells per lane, x-shifted values
  *             taken from overlapping aligned vector loads (needs
  *             nx % 2^(variant-4) == 0)
- *             8, 9, 10 = T = 2, 3, 4 steps per launch (temporal blocking in
+ *             8 .. 12 = T = 2 .. 6 steps per launch (temporal blocking in
  *             registers): each wave of 64 lanes owns a strip of 64 - 2(T-1)
- *             columns and a segment of `rows` rows; block_x must be 64,
+ *             columns, rounded down to whole 32-byte (else 16-byte) pieces
+ *             of a stored row where that drops at most two columns, and a segment of
+ *             `rows` rows; T = 5 and 6 take no non-temporal loads; block_x must be 64,
  *             block_y (waves per workgroup) 1..4, rows 1..4096.  lbm_step(n)
  *             then makes n / T such launches and n % T one-step launches
  *             (with the one-step shape last set or found by lbm_tune).
@@ -125,11 +127,11 @@ typedef struct lbm_lattice lbm_lattice;
  *             same XCD (shared L2), 0 = hardware order
  *   flags     bit 0: non-temporal loads; bit 1: issue the next row's (variants
  *             0, 8, 9, 10) or next chunk's (variant 4) loads before colliding
- *             the current cells (variants 0, 4, 8, 9, 10 only); bit 2
- *             (variants 8, 9, 10 only): move values between neighbouring
+ *             the current cells (variants 0, 4, 8-12 only); bit 2
+ *             (variants 8-12 only): move values between neighbouring
  *             lanes with DPP whole-wave shifts instead of LDS shuffles; bit 3
- *             (variants 8, 9, 10 only, not with bit 1): issue the loads two
- *             rows ahead; bit 4 (variants 9 and 10 only, not with bit 0):
+ *             (variants 8-12 only, not with bit 1): issue the loads two
+ *             rows ahead; bit 4 (variants 9-12 only, not with bit 0):
  *             skewed pipeline, in which stage p works two rows behind stage
  *             p-1 instead of one, so that the T collisions of a row
  *             iteration do not depend on each other.
@@ -244,7 +246,7 @@ LBM_API lbm_status lbm_tune(lbm_lattice *lat, int32_t reps, lbm_launch *best, do
 /* Times n launches of the current shape (state unchanged; syncs); avg_us is
  * per launch, which covers lbm_steps_per_launch steps. */
 LBM_API lbm_status lbm_time_launches(lbm_lattice *lat, int32_t n, double *avg_us);
-/* Steps one launch of this shape advances (1, or T for variants 8-10);
+/* Steps one launch of this shape advances (1, or T for variants 8-12);
  * 0 if cfg is NULL.  Does not validate the shape. */
 LBM_API int32_t lbm_steps_per_launch(const lbm_launch *cfg);
 

@@ -99,19 +99,19 @@ lbm_launch default_single(const View &)
     return c;
 }
 
-// Large lattices (>= 2^22 cells): four steps per launch, 4 waves per
-// workgroup, 32-row segments, one row of loads ahead -- within a few per
-// cent of the tuned shape for every storage type.  Smaller lattices offer
-// too few strip segments to keep the GPU busy through the four-stage
-// pipeline and keep the one-step shape.
+// Large lattices (>= 2^22 cells): five steps per launch, 4 waves per
+// workgroup, 64-row segments, one row of loads ahead -- within ~10 % of
+// the tuned shape for every storage type.  Smaller lattices offer too few
+// strip segments to keep the GPU busy through the pipeline and keep the
+// one-step shape.
 lbm_launch default_launch(const View &v)
 {
     if ((int64_t)v.nx * v.ny < ((int64_t)1 << 22)) return default_single(v);
     lbm_launch c{};
-    c.variant = 10;
+    c.variant = 11;
     c.block_x = 64;
     c.block_y = 4;
-    c.rows = 32;
+    c.rows = 64;
     c.xcd_remap = 1;
     c.flags = 2;
     return c;
@@ -159,10 +159,10 @@ std::vector<lbm_launch> variant_candidates(const View &v, const lbm_launch &best
 std::vector<lbm_launch> multi_candidates(const View &v)
 {
     std::vector<lbm_launch> out;
-    for (int var = 8; var <= 10; ++var)
-        for (int by : {1, 2, 4})
-            for (int rows : {32, 64, 128, 176, 256})
-                for (int flags : {0, 2, 4, 6, 8, 12, 16, 18, 20, 28}) {
+    for (int var = 8; var <= 12; ++var)
+        for (int by : {1, 4})
+            for (int rows : {32, 64, 176, 256})
+                for (int flags : {0, 2, 4, 12, 18, 20}) {
                     lbm_launch c{};
                     c.variant = var;
                     c.block_x = 64;

@@ -30,6 +30,8 @@ size_t storage_bytes(int32_t storage);
 bool step_shape_supported(const View &v, const lbm_launch &cfg);
 // Steps one launch of this shape advances (several-steps-per-pass variants).
 int steps_per_launch(const lbm_launch &cfg);
+// Output columns of a T-step strip for a storage element of elem_bytes.
+int multi_strip_cols(int T, int elem_bytes);
 
 hipError_t launch_step(const View &v, const void *src, void *dst, const lbm_launch &cfg,
                        hipStream_t st);

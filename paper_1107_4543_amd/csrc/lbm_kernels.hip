@@ -47,7 +47,7 @@ struct StepArgs {
     void *dst;
     int32_t nx, ny, pitch, tiles_x;
     int32_t tile_h, rows, nblocks, xcd_remap;
-    int32_t nwaves, pad_;
+    int32_t nwaves, out_cols;
     int64_t plane;
     Relax<C> r;
     float scale, inv_scale;
@@ -470,12 +470,13 @@ __device__ __forceinline__ int wrap_mod(int v, int n)
     return v < 0 ? v + n : v;
 }
 
-// T steps of the strip whose output columns start at x0, rows y0 .. y0+len-1
-// of one lattice, by the calling wave (threadIdx.x = lane).
+// T steps of the strip whose cols output columns start at x0 (cols <=
+// 64 - 2(T-1)), rows y0 .. y0+len-1 of one lattice, by the calling wave
+// (threadIdx.x = lane; lane T-1 holds column x0).
 template <typename S, typename C, int T, int FLAGS>
 __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *__restrict__ dst, int nx, int ny,
                                            int pitch, int64_t plane, const Relax<C> &relax, float scale,
-                                           float inv_scale, int x0, int y0, int len)
+                                           float inv_scale, int x0, int cols, int y0, int len)
 {
     using R = typename Store<S>::raw;
     using W = typename Store<S>::wide;
@@ -494,7 +495,7 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
     const uint32_t c0 = (uint32_t)c * E;
     const uint32_t cm = (uint32_t)((c == 0 ? nx : c) - 1) * E;
     const uint32_t cp = (uint32_t)((c + 1 == nx) ? 0 : c + 1) * E;
-    const bool writes = lane >= T - 1 && lane <= 64 - T && xl < nx;
+    const bool writes = lane >= T - 1 && lane < T - 1 + cols && xl < nx;
     const uint64_t pb = (uint64_t)plane * E;
     const uint32_t rb = (uint32_t)pitch * E;
     const int iters = len + LAG * (T - 1);
@@ -665,7 +666,7 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
 template <typename S, typename C, int T, int FLAGS>
 __global__ void __launch_bounds__(256) k_step_multi(StepArgs<C> a)
 {
-    constexpr int OUT = 64 - 2 * (T - 1);
+    const int OUT = a.out_cols;
     int bid = blockIdx.x;
     if (a.xcd_remap) bid = remap_xcd(bid, a.nblocks);
     const int wave = bid * (int)blockDim.y + (int)threadIdx.y;
@@ -673,7 +674,7 @@ __global__ void __launch_bounds__(256) k_step_multi(StepArgs<C> a)
     const int strip = wave % a.tiles_x, seg = wave / a.tiles_x;
     const int y0 = seg * a.tile_h;
     strip_pass<S, C, T, FLAGS>((const char *)a.src, (char *)a.dst, a.nx, a.ny, a.pitch, a.plane, a.r, a.scale,
-                               a.inv_scale, strip * OUT, y0, min(a.tile_h, a.ny - y0));
+                               a.inv_scale, strip * OUT, OUT, y0, min(a.tile_h, a.ny - y0));
 }
 
 // ---- batched step over a pool of lattices ----------------------------------------
@@ -754,8 +755,8 @@ __global__ void __launch_bounds__(256) k_pool_multi(const PoolHeader *hdr, const
         if ((int64_t)(j + 1) * T > m->t_target - m->t_done) continue;
         const int par = (int)((m->cur0 + m->flips + j) & 1);
         strip_pass<S, C, T, FLAGS>((const char *)m->buf[par], (char *)m->buf[par ^ 1], m->nx, m->ny, m->pitch,
-                                   m->plane, member_relax<C>(m), m->scale, m->inv_scale, tile.x0, tile.y0,
-                                   tile.nrows);
+                                   m->plane, member_relax<C>(m), m->scale, m->inv_scale, tile.x0, tile.ncols,
+                                   tile.y0, tile.nrows);
     }
 }
 
@@ -1069,11 +1070,12 @@ hipError_t launch_step_typed(const View &v, const void *src, void *dst, const lb
     a.scale = (float)v.scale;
     a.inv_scale = (float)v.inv_scale;
     a.nwaves = 0;
-    a.pad_ = 0;
+    a.out_cols = 0;
     if (cfg.variant >= 8) {
-        // strips of 64 - 2(T-1) output columns, segments of `rows` rows, one wave each
+        // strips of multi_strip_cols output columns, segments of `rows` rows, one wave each
         const int T = cfg.variant - 6;
-        a.tiles_x = (v.nx + (64 - 2 * (T - 1)) - 1) / (64 - 2 * (T - 1));
+        a.out_cols = multi_strip_cols(T, (int)sizeof(typename Store<S>::raw));
+        a.tiles_x = (v.nx + a.out_cols - 1) / a.out_cols;
         a.tile_h = cfg.rows;
         const int segs = (v.ny + cfg.rows - 1) / cfg.rows;
         a.nwaves = a.tiles_x * segs;
@@ -1093,6 +1095,12 @@ hipError_t launch_step_typed(const View &v, const void *src, void *dst, const lb
         // skewed pipeline (bit 4), T = 3 and 4
         LBM_MULTI(3, 16) LBM_MULTI(3, 18) LBM_MULTI(3, 20) LBM_MULTI(3, 22) LBM_MULTI(3, 24) LBM_MULTI(3, 28)
         LBM_MULTI(4, 16) LBM_MULTI(4, 18) LBM_MULTI(4, 20) LBM_MULTI(4, 22) LBM_MULTI(4, 24) LBM_MULTI(4, 28)
+        // T = 5 and 6, loads not non-temporal
+#define LBM_MULTI_E(T_) LBM_MULTI(T_, 0) LBM_MULTI(T_, 2) LBM_MULTI(T_, 4) LBM_MULTI(T_, 6) LBM_MULTI(T_, 8) \
+                        LBM_MULTI(T_, 12) LBM_MULTI(T_, 16) LBM_MULTI(T_, 18) LBM_MULTI(T_, 20) LBM_MULTI(T_, 28)
+        LBM_MULTI_E(5)
+        LBM_MULTI_E(6)
+#undef LBM_MULTI_E
 #undef LBM_MULTI_T
 #undef LBM_MULTI
         default: return hipErrorInvalidValue;
@@ -1217,12 +1225,30 @@ size_t storage_bytes(int32_t storage)
     }
 }
 
-int steps_per_launch(const lbm_launch &cfg) { return cfg.variant >= 8 && cfg.variant <= 10 ? cfg.variant - 6 : 1; }
+int steps_per_launch(const lbm_launch &cfg) { return cfg.variant >= 8 && cfg.variant <= 12 ? cfg.variant - 6 : 1; }
+
+// Output columns of a strip: 64 - 2(T-1) lanes see all their neighbours for
+// T stages.  The count is rounded down to a whole number of 32-byte (else
+// 16-byte) pieces of a stored row when that costs at most two columns, so
+// that neighbouring strips' row stores meet on sector boundaries (measured:
+// 58 -> 56 columns at T = 4 is +17 % for FP32 and FP64 storage; larger cuts
+// cost more lanes than they gain).
+int multi_strip_cols(int T, int elem_bytes)
+{
+    const int raw = 64 - 2 * (T - 1);
+    for (int bytes : {32, 16}) {
+        const int a = elem_bytes >= bytes ? 1 : bytes / elem_bytes;
+        const int aligned = raw - raw % a;
+        if (raw - aligned <= 2) return aligned;
+    }
+    return raw;
+}
 
 bool step_shape_supported(const View &v, const lbm_launch &cfg)
 {
-    if (cfg.variant >= 8 && cfg.variant <= 10) {
+    if (cfg.variant >= 8 && cfg.variant <= 12) {
         // several steps per pass: one wave per strip and segment
+        if (cfg.variant >= 11 && (cfg.flags & 1)) return false;   // T = 5, 6: no non-temporal loads
         return cfg.block_x == 64 && cfg.block_y >= 1 && cfg.block_y <= 4 && cfg.rows >= 1 &&
                cfg.rows <= 4096 && (cfg.xcd_remap == 0 || cfg.xcd_remap == 1) && cfg.flags >= 0 &&
                cfg.flags <= 29 && !((cfg.flags & 8) && (cfg.flags & 2)) &&

@@ -98,13 +98,17 @@ int tile_cols(const lbm_pool_shape &sh, const lbm_lattice *L)
     return L->v.nx <= seg ? L->v.nx : seg;
 }
 
-// T-step strip tasks: 64 - 2(T-1) output columns by seg_rows rows.
-int strip_cols(const lbm_pool_shape &sh) { return 64 - 2 * (sh.steps_per_launch - 1); }
+// T-step strip tasks: multi_strip_cols output columns by seg_rows rows.
+int strip_cols(const lbm_pool_shape &sh, const lbm_lattice *L)
+{
+    static const int bytes[4] = {8, 4, 2, 2};   // storage element size by lbm_storage
+    return lbm::multi_strip_cols(sh.steps_per_launch, bytes[L->v.storage]);
+}
 
 int tasks_of(const lbm_pool_shape &sh, const lbm_lattice *L)
 {
     if (sh.steps_per_launch < 2) return 0;
-    const int w = strip_cols(sh);
+    const int w = strip_cols(sh, L);
     return ((L->v.nx + w - 1) / w) * ((L->v.ny + sh.seg_rows - 1) / sh.seg_rows);
 }
 
@@ -178,7 +182,7 @@ lbm_status upload(lbm_pool *P)
                 all.push_back(t);
             }
         if (P->shape.steps_per_launch > 1) {
-            const int w = strip_cols(P->shape), sr = P->shape.seg_rows;
+            const int w = strip_cols(P->shape, L), sr = P->shape.seg_rows;
             for (int y0 = 0; y0 < L->v.ny; y0 += sr)
                 for (int x0 = 0; x0 < L->v.nx; x0 += w) {
                     T t{};
