@@ -84,8 +84,8 @@ def read_traffic(workload, storage, launch):
 
 # Launch shapes lbm_tune selected for the 4096^2 wave workload on MI355X
 # (variants 11 and 12: five and six steps per pass); --tune searches again.
-DEFAULT_LAUNCH = {"f32": "12,64,4,176,1,2", "f16": "11,64,1,64,1,0", "bf16": "11,64,1,64,1,2",
-                  "f64": "12,64,1,176,1,12"}
+DEFAULT_LAUNCH = {"f32": "12,64,4,176,1,2", "f16": "12,64,4,64,1,0", "bf16": "11,64,1,64,1,0",
+                  "f64": "11,64,4,176,1,12"}
 
 
 def build_waves4096(storage):
@@ -222,10 +222,19 @@ def bench_batch256(args):
     pool.close()
 
     lups = cells * steps
-    # each member reads and writes its nine planes once per launch it takes:
-    # steps // T launches of T steps and steps % T one-step launches
+    # each member reads and writes its nine planes once per launch it takes;
+    # replay the pool's chunking (loops of T 2^m steps, powers of two below
+    # T) to count its T-step and one-step launches
     T = shape["steps_per_launch"]
-    member_launches = steps // T + steps % T
+    member_launches, left = 0, steps
+    while left > 0:
+        lim = min(left, shape["graph_steps"])
+        kk = T if (T > 1 and lim >= T) else 1
+        while kk * 2 <= lim:
+            kk *= 2
+        q = kk // T if (T > 1 and kk >= T) else 0
+        member_launches += q + (kk - q * T)
+        left -= kk
     alg = 72 * cells * member_launches
     return {
         "metric": METRIC, "value": round(lups / (ms_batched / 1e3) / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,

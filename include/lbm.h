@@ -101,8 +101,10 @@ typedef struct lbm_desc {
 typedef struct lbm_lattice lbm_lattice;
 
 /* Launch shape of the fused step kernel (chosen by lbm_tune or set by hand;
- * a new lattice of at least 2^22 cells starts with {11, 64, 4, 64, 1, 2},
- * five steps per launch, a smaller one with {0, 64, 4, 1, 1, 0}).
+ * a new lattice of at least 2^22 cells starts with a several-steps shape
+ * by storage type: FP32 {12, 64, 4, 176, 1, 2}, FP16 {12, 64, 4, 64, 1, 0},
+ * BF16 {11, 64, 1, 64, 1, 0}, FP64 {11, 64, 4, 176, 1, 12}; a smaller one
+ * with {0, 64, 4, 1, 1, 0}).
  *   variant   0 = one cell per lane (nine direct loads),
  *             1, 2, 3 = 2, 4, 8 consecutive cells per lane (aligned vector
  *             loads, x-shift by cross-lane exchange; needs nx % 2^variant == 0
@@ -255,11 +257,12 @@ LBM_API int32_t lbm_steps_per_launch(const lbm_launch *cfg);
  * A pool advances its members (lattices of any size, rates and storage)
  * with persistent launches per storage class: with steps_per_launch T > 1
  * one launch advances every member by T steps (strip tasks of the
- * several-steps-per-pass kernel, see lbm_launch variants 8-10) and a member
+ * several-steps-per-pass kernel, see lbm_launch variants 8-12) and a member
  * whose remaining count is not a multiple of T takes its last steps in
- * one-step launches; step loops of power-of-two lengths up to graph_steps
- * are recorded once as HIP graphs and replayed (lbm_pool_step(n) runs n
- * steps as a few such replays).  Each
+ * one-step launches; step loops of T 2^m steps (or powers of two below T)
+ * up to graph_steps, each with as many one-step launches as its members
+ * need, are recorded once as HIP graphs and replayed
+ * (lbm_pool_step(n) runs n steps as a few such replays).  Each
  * member carries its own step count: a member added with nsteps stops after
  * exactly nsteps steps, independently of the others, and is then returned by
  * lbm_pool_poll.  Members join and leave between lbm_pool_step calls
@@ -281,14 +284,14 @@ typedef struct lbm_pool lbm_pool;
  *   block        threads per workgroup of the one-step launch, multiple of
  *                64, 64 .. 1024
  *   grid         workgroups of a persistent launch (both kinds), 1 .. 2^20
- *   graph_steps  longest recorded step loop (rounded down to a power of
- *                two when used), 1 .. 1024
- *   steps_per_launch  T = 1, 2 or 4; T > 1 adds strip tasks of 64 - 2(T-1)
- *                columns and seg_rows rows, one wave each
+ *   graph_steps  longest recorded step loop (a loop is T 2^m steps, or a
+ *                power of two below T), 1 .. 1024
+ *   steps_per_launch  T = 1, 2, 4, 5 or 6; T > 1 adds strip tasks (columns
+ *                as for lbm_launch variants 8-12) of seg_rows rows, one wave
+ *                each
  *   seg_rows     rows of a strip task, 1 .. 4096
  *   waves        waves per workgroup of the T-step launch, 1 .. 4
- *   flags        T-step kernel flags as in lbm_launch (0 .. 13, not bits 1
- *                and 3 together)
+ *   flags        T-step kernel flags as in lbm_launch: 0, 2, 4 or 12
  * The tile table holds the one-step tiles and, for T > 1, the strip tasks
  * of every unfinished member. */
 typedef struct lbm_pool_shape {

@@ -99,21 +99,24 @@ lbm_launch default_single(const View &)
     return c;
 }
 
-// Large lattices (>= 2^22 cells): five steps per launch, 4 waves per
-// workgroup, 64-row segments, one row of loads ahead -- within ~10 % of
-// the tuned shape for every storage type.  Smaller lattices offer too few
-// strip segments to keep the GPU busy through the pipeline and keep the
-// one-step shape.
+// Large lattices (>= 2^22 cells): several steps per launch with the shape
+// measured fastest for the storage type on 4096^2 and 8192^2 lattices
+// (variant, waves per workgroup, segment rows, flags): FP32 (12, 4, 176, 2),
+// FP16 (12, 4, 64, 0), BF16 (11, 1, 64, 0), FP64 (11, 4, 176, 12).  Smaller
+// lattices offer too few strip segments to keep the GPU busy through the
+// pipeline and keep the one-step shape.
 lbm_launch default_launch(const View &v)
 {
     if ((int64_t)v.nx * v.ny < ((int64_t)1 << 22)) return default_single(v);
     lbm_launch c{};
-    c.variant = 11;
     c.block_x = 64;
-    c.block_y = 4;
-    c.rows = 64;
     c.xcd_remap = 1;
-    c.flags = 2;
+    switch (v.storage) {
+    case LBM_STORE_F32: c.variant = 12; c.block_y = 4; c.rows = 176; c.flags = 2; break;
+    case LBM_STORE_F16: c.variant = 12; c.block_y = 4; c.rows = 64; c.flags = 0; break;
+    case LBM_STORE_BF16: c.variant = 11; c.block_y = 1; c.rows = 64; c.flags = 0; break;
+    default: c.variant = 11; c.block_y = 4; c.rows = 176; c.flags = 12; break;
+    }
     return c;
 }
 

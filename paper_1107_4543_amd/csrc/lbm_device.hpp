@@ -18,9 +18,10 @@
 //     dQ = |j|^2/rho - |j0|^2/rho0 = (2 j0.j' + |j'|^2 - Q0 rho') / rho
 //     dP = (jx^2 - jy^2)/rho - P0 ,  dX = jx jy / rho - X0   (same pattern)
 // with Q0 = |j0|^2/rho0, P0 = (j0x^2 - j0y^2)/rho0, X0 = j0x j0y/rho0.
-// M and M^T have integer entries, so both transforms are add/sub chains;
-// the only multiplications are by the six per-lattice constants s_k / D_k,
-// and the only division is 1/rho.
+// M and M^T have integer entries, so both transforms are add/sub chains
+// (small integer multiples go into fused multiply-adds); besides the
+// quadratic terms of the equilibrium, the only multiplications are by the
+// per-lattice constants s_k / D_k, and the only division is 1/rho.
 //
 // Velocity order: v_0=(0,0) v_1=(1,0) v_2=(0,1) v_3=(-1,0) v_4=(0,-1)
 //                 v_5=(1,1) v_6=(-1,1) v_7=(-1,-1) v_8=(1,-1).
@@ -97,10 +98,23 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 // (the |j|^2 terms and the density in the denominator), so that every
 // intermediate value is exactly 2^p times its unscaled counterpart and dg
 // comes out scaled by 2^p with the same rounding.
+//
+// The relaxation terms a_k = (s_k / D_k)(dmeq_k - m'_k) are written in the
+// populations' partial sums, with the conserved moments substituted
+// (a = axis sum, b = diagonal sum, rho' = g_0 + a + b):
+//     a_e   = lam_e   (2 g_0 - a - 4 b + 3 dQ)
+//     a_eps = 3 lam_eps (a - g_0 - dQ)
+//     a_qx  = lam_q   (dx1 - 2 dxd)      (dx1 = g_1 - g_3, dxd = sum_diag c_x g)
+//     a_pxx = lam_nu  (dP - pxx),  a_pxy = lam_nu (dX - pxy)
+// with dQ, dP, dX numerators N over rho = rho0 + t rho':
+//     N_Q = ax + ay - Q0 rho',  N_P = ax - ay - P0 rho',  ax = jx (t jx + 2 j0x)
+//     N_X = jy (t jx + j0x) + j0y jx - X0 rho'
+// (the same quantities as the equilibrium above, in fewer operations; the
+// kinetic moments e, eps, q are never formed).
 template <typename T>
 __device__ __forceinline__ void collide_increment(const T g[9], const Relax<T> &r, T t, T dg[9])
 {
-    // m' = M g
+    // partial sums of the populations
     const T s13 = g[1] + g[3], s24 = g[2] + g[4];
     const T s57 = g[5] + g[7], s68 = g[6] + g[8];
     const T a = s13 + s24;                              // axis sum
@@ -111,29 +125,27 @@ __device__ __forceinline__ void collide_increment(const T g[9], const Relax<T> &
     const T dxd = d57 + d86;                            // sum_diag c_x g
     const T dyd = d57 - d86;                            // sum_diag c_y g
     const T jx = dx1 + dxd, jy = dy1 + dyd;
-    const T e = fmad(T(2), b, fmad(T(-4), g[0], -a));
-    const T eps = fmad(T(4), g[0], fmad(T(-2), a, b));
     const T pxx = s13 - s24;
     const T pxy = s57 - s68;
-    const T qx = fmad(T(-2), dx1, dxd), qy = fmad(T(-2), dy1, dyd);
-    // equilibrium deviation (Sec. 2.3) about (rho0, j0), one reciprocal
+    // equilibrium numerators (Sec. 2.3) about (rho0, j0), one reciprocal
     const T inv = recip(fmad(t, rho, r.rho0));
-    const T tjx = t * jx, tjy = t * jy;
-    const T dQ = fmad(-r.Q0, rho, fmad(T(2), fmad(r.j0x, jx, r.j0y * jy), fmad(tjx, jx, tjy * jy))) * inv;
-    const T dP = fmad(-r.P0, rho, fmad(T(2), fmad(r.j0x, jx, -(r.j0y * jy)), fmad(tjx, jx, -(tjy * jy)))) * inv;
-    const T dX = fmad(-r.X0, rho, fmad(r.j0x, jy, fmad(r.j0y, jx, tjx * jy))) * inv;
-    // (s_k / D_k) (dmeq_k - m'_k), k = 3..8
-    const T a3 = r.lam_e * (fmad(T(3), dQ, T(-2) * rho) - e);
-    const T a4 = r.lam_eps * (fmad(T(-3), dQ, rho) - eps);
-    const T a5 = r.lam_q * (-jx - qx);
-    const T a6 = r.lam_q * (-jy - qy);
-    const T a7 = r.lam_nu * (dP - pxx);
-    const T a8 = r.lam_nu * (dX - pxy);
+    const T ax = jx * fmad(t, jx, T(2) * r.j0x);
+    const T ay = jy * fmad(t, jy, T(2) * r.j0y);
+    const T nQ = fmad(-r.Q0, rho, ax) + ay;
+    const T nP = fmad(-r.P0, rho, ax) - ay;
+    const T nX = fmad(-r.X0, rho, fmad(r.j0y, jx, jy * fmad(t, jx, r.j0x)));
+    // relaxation terms a_k, k = 3..8
+    const T a3 = r.lam_e * fmad(nQ, T(3) * inv, fmad(T(-4), b, fmad(T(2), g[0], -a)));
+    const T a4 = (T(3) * r.lam_eps) * fmad(-nQ, inv, a - g[0]);
+    const T a5 = r.lam_q * fmad(T(-2), dxd, dx1);
+    const T a6 = r.lam_q * fmad(T(-2), dyd, dy1);
+    const T x7 = fmad(nP, inv, -pxx);
+    const T x8 = fmad(nX, inv, -pxy);
     // dg = M^T a
     const T A = fmad(T(-2), a4, -a3);
     const T B = fmad(T(2), a3, a4);
-    const T A7 = A + a7, Am7 = A - a7;
-    const T B8 = B + a8, Bm8 = B - a8;
+    const T A7 = fmad(r.lam_nu, x7, A), Am7 = fmad(-r.lam_nu, x7, A);
+    const T B8 = fmad(r.lam_nu, x8, B), Bm8 = fmad(-r.lam_nu, x8, B);
     const T p56 = a5 + a6, m56 = a5 - a6;
     dg[0] = T(4) * (a4 - a3);
     dg[1] = fmad(T(-2), a5, A7);

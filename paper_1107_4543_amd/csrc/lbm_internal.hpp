@@ -86,10 +86,12 @@ struct PoolHeader {
 };
 
 // Launch schedule of a recorded chunk of kk steps with T steps per T-step
-// launch: kk / T T-step launches, then the one-step launches that members
-// finishing inside the chunk need.  A member with rem steps left takes
-// q = min(rem / T, kk / T) T-step launches and span - q T one-step launches,
-// span = min(rem, kk); its source buffer alternates with every launch.
+// launch: floor(kk / T) T-step launches, then at most T - 1 one-step
+// launches (as many as the members need; chunk_single_launches bounds it).  A
+// member with rem steps left takes q = min(rem / T, kk / T) T-step launches
+// and span - q T one-step launches, span = min(rem, kk): kk mod T (< T) if
+// it stays, rem mod T (< T) if it finishes in the chunk.  Its source buffer
+// alternates with every launch it takes.
 __host__ __device__ inline int chunk_multi_launches(int kk, int T) { return T > 1 && kk >= T ? kk / T : 0; }
 __host__ __device__ inline int chunk_single_launches(int kk, int T) { return T > 1 && kk >= T ? T - 1 : kk; }
 __host__ __device__ inline int64_t member_multi(int64_t rem, int kk, int T)

@@ -126,6 +126,77 @@ __device__ __forceinline__ void store9(char *__restrict__ dst, uint64_t pb, uint
     for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(Store<S>::narrow(w[i]), (R *)(dst + i * pb + off));
 }
 
+// gather9 / store9 for rows that are the same on every lane of the wave: the
+// plane and row part of each address is one wave-uniform pointer per row
+// (readfirstlane keeps the compiler from folding it into per-lane 64-bit
+// sums), so every access is a scalar base plus the lane's 32-bit column
+// offset and the address costs no vector instruction.
+// A raw buffer resource for the bytes [base, base + bytes): an access through
+// it is the resource's (scalar) base plus the lane's 32-bit offset, added by
+// the memory unit.  Word 3 selects 32-bit raw data (the value CDNA uses for
+// untyped buffers); offsets are never out of range here.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const char *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)bytes, 0x00020000);
+}
+
+constexpr int kBufNT = 2;   // cache-policy bits of a non-temporal access
+typedef unsigned int buf_u32x2 __attribute__((__vector_size__(8)));
+
+template <typename S, bool NT>
+__device__ __forceinline__ typename Store<S>::wide ld_buf(__amdgpu_buffer_rsrc_t rs, uint32_t off)
+{
+    using R = typename Store<S>::raw;
+    constexpr int aux = NT ? kBufNT : 0;
+    if constexpr (sizeof(R) == 8)
+        return Store<S>::widen(__builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, aux)));
+    else if constexpr (sizeof(R) == 4)
+        return Store<S>::widen(__builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, aux)));
+    else
+        return Store<S>::widen(__builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, aux)));
+}
+
+template <typename S>
+__device__ __forceinline__ void st_buf(__amdgpu_buffer_rsrc_t rs, uint32_t off, typename Store<S>::wide v)
+{
+    using R = typename Store<S>::raw;
+    const R x = Store<S>::narrow(v);
+    if constexpr (sizeof(R) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(buf_u32x2, x), rs, off, 0, kBufNT);
+    else if constexpr (sizeof(R) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), rs, off, 0, kBufNT);
+    else
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, x), rs, off, 0, kBufNT);
+}
+
+// gather9 / store9 for rows that are the same on every lane of the wave
+// (rb = bytes of a row): one buffer resource per plane and row, so the
+// addresses cost scalar instructions only and the lanes supply their
+// column offsets.
+template <typename S, bool NT>
+__device__ __forceinline__ void gather9_uniform_rows(const char *__restrict__ src, uint64_t pb, uint32_t rb,
+                                                     uint32_t r0, uint32_t rm, uint32_t rp, uint32_t c0,
+                                                     uint32_t cm, uint32_t cp, typename Store<S>::wide w[9])
+{
+    w[0] = ld_buf<S, NT>(row_rsrc(src + (0 * pb + r0), rb), c0);
+    w[1] = ld_buf<S, NT>(row_rsrc(src + (1 * pb + r0), rb), cm);
+    w[2] = ld_buf<S, NT>(row_rsrc(src + (2 * pb + rm), rb), c0);
+    w[3] = ld_buf<S, NT>(row_rsrc(src + (3 * pb + r0), rb), cp);
+    w[4] = ld_buf<S, NT>(row_rsrc(src + (4 * pb + rp), rb), c0);
+    w[5] = ld_buf<S, NT>(row_rsrc(src + (5 * pb + rm), rb), cm);
+    w[6] = ld_buf<S, NT>(row_rsrc(src + (6 * pb + rm), rb), cp);
+    w[7] = ld_buf<S, NT>(row_rsrc(src + (7 * pb + rp), rb), cp);
+    w[8] = ld_buf<S, NT>(row_rsrc(src + (8 * pb + rp), rb), cm);
+}
+
+template <typename S>
+__device__ __forceinline__ void store9_uniform_row(char *__restrict__ dst, uint64_t pb, uint32_t rb, uint32_t row,
+                                                   uint32_t col, const typename Store<S>::wide w[9])
+{
+#pragma unroll
+    for (int i = 0; i < 9; ++i) st_buf<S>(row_rsrc(dst + (i * pb + row), rb), col, w[i]);
+}
+
 // One cell per lane: nine direct (possibly misaligned) loads.
 // FLAGS bit 0: non-temporal loads; bit 1: the nine loads of the lane's next
 // row are issued before the current row is collided and stored.
@@ -499,11 +570,17 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
     const uint64_t pb = (uint64_t)plane * E;
     const uint32_t rb = (uint32_t)pitch * E;
     const int iters = len + LAG * (T - 1);
-    auto gather = [&](int r, W w[9]) {
-        const int y = wrap_mod(r, ny);
+    const int r_first = y0 - (T - 1);
+    // Stage 0 gathers rows r_first, r_first + 1, ... in order, so a running
+    // wrapped row index (wave-uniform, like x0 and y0) replaces a modulo.
+    int yg = wrap_mod(r_first, ny);
+    auto gather_next = [&](W w[9]) {
+        const int y = yg;
         const int ym = (y == 0 ? ny : y) - 1;
         const int yp = (y + 1 == ny) ? 0 : y + 1;
-        gather9<S, NT>(src, pb, (uint32_t)y * rb, (uint32_t)ym * rb, (uint32_t)yp * rb, c0, cm, cp, w);
+        gather9_uniform_rows<S, NT>(src, pb, rb, (uint32_t)y * rb, (uint32_t)ym * rb, (uint32_t)yp * rb, c0, cm, cp,
+                                    w);
+        yg = yp;
     };
     // outputs of stage p kept for stage p + 1: populations 2, 5, 6 of the row
     // before the last one produced, and 0, 1, 3, 2, 5, 6 of the last one
@@ -521,10 +598,8 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
         for (int i = 0; i < 9; ++i) r1[p][i] = W(0);
     }
     W ahead[AHEAD > 0 ? AHEAD : 1][9];
-    const int r_first = y0 - (T - 1);
 #pragma unroll
-    for (int d = 0; d < AHEAD; ++d)
-        if (d < iters) gather(r_first + d, ahead[d]);
+    for (int d = 0; d < AHEAD; ++d) gather_next(ahead[d]);   // AHEAD <= 2 < iters
     // One row of the pipeline.  Before iteration 2(T-1) the later stages
     // have no rows yet and stop early (STEADY = false); afterwards every
     // stage runs and the body has no branches, so the loop can be unrolled
@@ -539,11 +614,12 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
         if constexpr (AHEAD > 0) {
 #pragma unroll
             for (int i = 0; i < 9; ++i) w[i] = slot[i];
-            // unconditional (rows past the segment wrap and are never
-            // used): no branch, so the waits for these loads stay exact
-            gather(r + AHEAD, slot);
+            // row r + AHEAD, unconditional (rows past the segment wrap and
+            // are never used): no branch, so the waits for these loads
+            // stay exact
+            gather_next(slot);
         } else {
-            gather(r, w);
+            gather_next(w);                             // row r
         }
         cell_update<S, C>(w, relax, scale, inv_scale);
 #pragma unroll
@@ -577,7 +653,7 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
 #pragma unroll
             for (int i = 0; i < 9; ++i) w[i] = in[i];
             cell_update<S, C>(w, relax, scale, inv_scale);
-            if (p == T - 1 && writes) store9<S>(dst, pb, (uint32_t)(r - (T - 1)) * rb + c0, w);
+            if (p == T - 1 && writes) store9_uniform_row<S>(dst, pb, rb, (uint32_t)(r - (T - 1)) * rb, c0, w);
         }
     };
     // The skewed pipeline's row: every stage reads only registers filled in
@@ -590,9 +666,9 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
         if constexpr (AHEAD > 0) {
 #pragma unroll
             for (int i = 0; i < 9; ++i) w[i] = slot[i];
-            gather(r + AHEAD, slot);
+            gather_next(slot);                          // row r + AHEAD
         } else {
-            gather(r, w);
+            gather_next(w);                             // row r
         }
         cell_update<S, C>(w, relax, scale, inv_scale);
         W res[T > 1 ? T - 1 : 1][9];
@@ -611,7 +687,7 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
                 in[7] = from_right<DPP>(r1[p - 1][7]);
                 in[8] = from_left<DPP>(r1[p - 1][8]);
                 cell_update<S, C>(in, relax, scale, inv_scale);
-                if (p == T - 1 && writes) store9<S>(dst, pb, (uint32_t)(r - 2 * (T - 1)) * rb + c0, in);
+                if (p == T - 1 && writes) store9_uniform_row<S>(dst, pb, rb, (uint32_t)(r - 2 * (T - 1)) * rb, c0, in);
             } else {
 #pragma unroll
                 for (int i = 0; i < 9; ++i) in[i] = W(0);
@@ -669,7 +745,9 @@ __global__ void __launch_bounds__(256) k_step_multi(StepArgs<C> a)
     const int OUT = a.out_cols;
     int bid = blockIdx.x;
     if (a.xcd_remap) bid = remap_xcd(bid, a.nblocks);
-    const int wave = bid * (int)blockDim.y + (int)threadIdx.y;
+    // one wave per strip segment (blockDim.x is the wave size): the index
+    // is uniform across the wave, which readfirstlane states to the compiler
+    const int wave = __builtin_amdgcn_readfirstlane(bid * (int)blockDim.y + (int)threadIdx.y);
     if (wave >= a.nwaves) return;                       // whole waves only
     const int strip = wave % a.tiles_x, seg = wave / a.tiles_x;
     const int y0 = seg * a.tile_h;
@@ -749,7 +827,8 @@ __global__ void __launch_bounds__(256) k_pool_multi(const PoolHeader *hdr, const
 {
     const int begin = hdr->mbegin[cls], end = hdr->mend[cls];
     const int nw = (int)(gridDim.x * blockDim.y);
-    for (int ti = begin + (int)(blockIdx.x * blockDim.y + threadIdx.y); ti < end; ti += nw) {
+    const int w0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * blockDim.y + threadIdx.y));   // one wave per task
+    for (int ti = begin + w0; ti < end; ti += nw) {
         const PoolTile tile = tiles[ti];                 // wave-uniform
         const PoolMember *m = mem + tile.member;
         if ((int64_t)(j + 1) * T > m->t_target - m->t_done) continue;
@@ -1340,9 +1419,11 @@ void *pool_multi_typed(int T, int flags)
 {
 #define LBM_PM(T_, F_) \
     if (T == T_ && flags == F_) return reinterpret_cast<void *>(&k_pool_multi<S, C, T_, F_>);
-#define LBM_PM_T(T_) LBM_PM(T_, 0) LBM_PM(T_, 2) LBM_PM(T_, 4) LBM_PM(T_, 6) LBM_PM(T_, 8) LBM_PM(T_, 12)
+#define LBM_PM_T(T_) LBM_PM(T_, 0) LBM_PM(T_, 2) LBM_PM(T_, 4) LBM_PM(T_, 12)
     LBM_PM_T(2)
     LBM_PM_T(4)
+    LBM_PM_T(5)
+    LBM_PM_T(6)
 #undef LBM_PM_T
 #undef LBM_PM
     return nullptr;

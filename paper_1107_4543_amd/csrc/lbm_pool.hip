@@ -79,7 +79,7 @@ struct lbm_pool {
     lbm_pool_shape shape{256, 512, 65536, 256, 4, 32, 4, 2};
     std::vector<Slot> slots;
     std::vector<int> finishing;      // slot indices in completion order
-    std::map<std::tuple<unsigned, int, int, int>, GraphEntry> graphs;   // (class mask, steps, grids)
+    std::map<std::tuple<unsigned, int, int, int, int>, GraphEntry> graphs;   // (class mask, steps, one-step launches, grids)
 };
 
 namespace {
@@ -258,14 +258,16 @@ int multi_grid(const lbm_pool *P)
 }
 
 // Records a step loop of `len` steps: the chunk schedule of
-// lbm_internal.hpp (len / T T-step launches, then the one-step launches,
-// one node per class in `mask`, each depending on the previous launch),
-// then the commit kernel.
-lbm_status get_graph(lbm_pool *P, unsigned mask, int len, hipGraphExec_t *out)
+// lbm_internal.hpp (len / T T-step launches, then `nsingle` of its one-step
+// launches, one node per class in `mask`, each depending on the previous
+// launch), then the commit kernel.  The one-step launches a member takes in
+// the chunk come first, so nsingle only has to cover the largest such count
+// among the members.
+lbm_status get_graph(lbm_pool *P, unsigned mask, int len, int nsingle, hipGraphExec_t *out)
 {
     const int grid = launch_grid(P), mgrid = multi_grid(P);
     const int T = P->shape.steps_per_launch;
-    auto key = std::make_tuple(mask, len, grid, mgrid);
+    auto key = std::make_tuple(mask, len, nsingle, grid, mgrid);
     auto it = P->graphs.find(key);
     if (it != P->graphs.end()) {
         *out = it->second.exec;
@@ -278,7 +280,7 @@ lbm_status get_graph(lbm_pool *P, unsigned mask, int len, hipGraphExec_t *out)
     const lbm::PoolHeader *hdr = P->d_hdr;
     const lbm::PoolMember *mem = P->d_mem;
     const lbm::PoolTile *tiles = P->d_tiles;
-    const int nmulti = lbm::chunk_multi_launches(len, T), nsingle = lbm::chunk_single_launches(len, T);
+    const int nmulti = lbm::chunk_multi_launches(len, T);
     for (int k = 0; k < nmulti + nsingle; ++k) {
         cur.clear();
         const bool multi = k < nmulti;
@@ -330,12 +332,21 @@ lbm_status get_graph(lbm_pool *P, unsigned mask, int len, hipGraphExec_t *out)
 }
 
 // Advances every active member by min(kk, remaining) with one recorded loop
-// of kk steps; kk is a power of two <= graph_steps.
+// of kk steps (kk <= graph_steps), holding as many one-step launches as the
+// members need in it.
 lbm_status run_chunk(lbm_pool *P, int kk)
 {
     hipError_t e;
     hipGraphExec_t ex;
-    lbm_status st = get_graph(P, P->class_mask, kk, &ex);
+    const int T = P->shape.steps_per_launch;
+    int64_t need = 0;
+    for (const Slot &s : P->slots) {
+        if (!s.lat || s.finishing) continue;
+        const int64_t rem = s.t_target - s.t_done;
+        need = std::max(need, std::min<int64_t>(rem, kk) - lbm::member_multi(rem, kk, T) * T);
+    }
+    need = std::min<int64_t>(need, lbm::chunk_single_launches(kk, T));
+    lbm_status st = get_graph(P, P->class_mask, kk, (int)need, &ex);
     if (st != LBM_OK) return st;
     if ((e = hipGraphLaunch(ex, P->stream)) != hipSuccess) return phip(e, "hipGraphLaunch");
     for (int i = 0; i < P->max_members; ++i) {
@@ -358,7 +369,8 @@ lbm_status run_chunk(lbm_pool *P, int kk)
 bool valid_shape(const lbm_pool_shape &s)
 {
     const bool multi_ok = s.steps_per_launch == 1 ||
-                          ((s.steps_per_launch == 2 || s.steps_per_launch == 4) && s.seg_rows >= 1 &&
+                          ((s.steps_per_launch == 2 || s.steps_per_launch == 4 || s.steps_per_launch == 5 ||
+                            s.steps_per_launch == 6) && s.seg_rows >= 1 &&
                            s.seg_rows <= 4096 && s.waves >= 1 && s.waves <= 4 &&
                            lbm::pool_multi_kernel(LBM_STORE_F32 * 2 + LBM_COMPUTE_F32, s.steps_per_launch, s.flags));
     return s.tile_cells >= 64 && s.tile_cells <= (1 << 22) && s.block >= 64 && s.block <= 1024 && s.block % 64 == 0 &&
@@ -516,10 +528,17 @@ lbm_status lbm_pool_step(lbm_pool *pool, int64_t nsteps)
         if (max_rem == 0) break;
         lbm_status st = upload(pool);
         if (st != LBM_OK) return st;
-        // the longest recorded loop (a power of two) that fits
+        // the longest recorded loop that fits: T 2^m steps (only T-step
+        // launches for members that stay), or a power of two below T
         const int64_t lim = std::min<int64_t>({nsteps, (int64_t)pool->shape.graph_steps, max_rem});
+        const int T = pool->shape.steps_per_launch;
         int kk = 1;
-        while ((int64_t)kk * 2 <= lim) kk *= 2;
+        if (T > 1 && lim >= T) {
+            kk = T;
+            while ((int64_t)kk * 2 <= lim) kk *= 2;
+        } else {
+            while ((int64_t)kk * 2 <= lim) kk *= 2;
+        }
         if ((st = run_chunk(pool, kk)) != LBM_OK) return st;
         nsteps -= kk;
         // finished members keep their (now idle) tiles until the next upload
@@ -680,10 +699,10 @@ lbm_status lbm_pool_tune(lbm_pool *pool, int32_t reps, lbm_pool_shape *best, dou
                 }
             }
     // several steps per launch (their left-over steps use the best one-step tiles)
-    for (int T : {2, 4})
+    for (int T : {2, 4, 5, 6})
         for (int seg : {32, 64, 128})
-            for (int waves : {1, 2, 4})
-                for (int flags : {0, 2, 4, 12})
+            for (int waves : {1, 4})
+                for (int flags : {0, 2, 12})
                     for (int grid : {4096, 16384, 65536}) {
                         lbm_pool_shape s = single;
                         s.steps_per_launch = T;
