@@ -102,8 +102,8 @@ typedef struct lbm_lattice lbm_lattice;
 
 /* Launch shape of the fused step kernel (chosen by lbm_tune or set by hand;
  * a new lattice of at least 2^22 cells starts with a several-steps shape
- * by storage type: FP32 {12, 64, 4, 176, 1, 2}, FP16 {12, 64, 4, 64, 1, 0},
- * BF16 {11, 64, 1, 64, 1, 0}, FP64 {11, 64, 4, 176, 1, 12}; a smaller one
+ * by storage type: FP32 {13, 64, 4, 176, 1, 2}, FP16 {12, 64, 4, 64, 1, 0},
+ * BF16 {12, 64, 4, 64, 1, 2}, FP64 {11, 64, 4, 176, 1, 12}; a smaller one
  * with {0, 64, 4, 1, 1, 0}).
  *   variant   0 = one cell per lane (nine direct loads),
  *             1, 2, 3 = 2, 4, 8 consecutive cells per lane (aligned vector
@@ -114,11 +114,12 @@ typedef struct lbm_lattice lbm_lattice;
  *             5, 6, 7 = 2, 4, 8 consecutive cells per lane, x-shifted values
  *             taken from overlapping aligned vector loads (needs
  *             nx % 2^(variant-4) == 0)
- *             8 .. 12 = T = 2 .. 6 steps per launch (temporal blocking in
+ *             8 .. 13 = T = 2 .. 7 steps per launch (temporal blocking in
  *             registers): each wave of 64 lanes owns a strip of 64 - 2(T-1)
  *             columns, rounded down to whole 32-byte (else 16-byte) pieces
  *             of a stored row where that drops at most two columns, and a segment of
- *             `rows` rows; T = 5 and 6 take no non-temporal loads; block_x must be 64,
+ *             `rows` rows; T = 5, 6 and 7 take no non-temporal loads, T = 7 no
+ *             skewed pipeline; block_x must be 64,
  *             block_y (waves per workgroup) 1..4, rows 1..4096.  lbm_step(n)
  *             then makes n / T such launches and n % T one-step launches
  *             (with the one-step shape last set or found by lbm_tune).
@@ -129,10 +130,10 @@ typedef struct lbm_lattice lbm_lattice;
  *             same XCD (shared L2), 0 = hardware order
  *   flags     bit 0: non-temporal loads; bit 1: issue the next row's (variants
  *             0, 8, 9, 10) or next chunk's (variant 4) loads before colliding
- *             the current cells (variants 0, 4, 8-12 only); bit 2
- *             (variants 8-12 only): move values between neighbouring
+ *             the current cells (variants 0, 4, 8-13 only); bit 2
+ *             (variants 8-13 only): move values between neighbouring
  *             lanes with DPP whole-wave shifts instead of LDS shuffles; bit 3
- *             (variants 8-12 only, not with bit 1): issue the loads two
+ *             (variants 8-13 only, not with bit 1): issue the loads two
  *             rows ahead; bit 4 (variants 9-12 only, not with bit 0):
  *             skewed pipeline, in which stage p works two rows behind stage
  *             p-1 instead of one, so that the T collisions of a row
@@ -248,7 +249,7 @@ LBM_API lbm_status lbm_tune(lbm_lattice *lat, int32_t reps, lbm_launch *best, do
 /* Times n launches of the current shape (state unchanged; syncs); avg_us is
  * per launch, which covers lbm_steps_per_launch steps. */
 LBM_API lbm_status lbm_time_launches(lbm_lattice *lat, int32_t n, double *avg_us);
-/* Steps one launch of this shape advances (1, or T for variants 8-12);
+/* Steps one launch of this shape advances (1, or T for variants 8-13);
  * 0 if cfg is NULL.  Does not validate the shape. */
 LBM_API int32_t lbm_steps_per_launch(const lbm_launch *cfg);
 
@@ -257,7 +258,7 @@ LBM_API int32_t lbm_steps_per_launch(const lbm_launch *cfg);
  * A pool advances its members (lattices of any size, rates and storage)
  * with persistent launches per storage class: with steps_per_launch T > 1
  * one launch advances every member by T steps (strip tasks of the
- * several-steps-per-pass kernel, see lbm_launch variants 8-12) and a member
+ * several-steps-per-pass kernel, see lbm_launch variants 8-13) and a member
  * whose remaining count is not a multiple of T takes its last steps in
  * one-step launches; step loops of T 2^m steps (or powers of two below T)
  * up to graph_steps, each with as many one-step launches as its members
@@ -286,8 +287,8 @@ typedef struct lbm_pool lbm_pool;
  *   grid         workgroups of a persistent launch (both kinds), 1 .. 2^20
  *   graph_steps  longest recorded step loop (a loop is T 2^m steps, or a
  *                power of two below T), 1 .. 1024
- *   steps_per_launch  T = 1, 2, 4, 5 or 6; T > 1 adds strip tasks (columns
- *                as for lbm_launch variants 8-12) of seg_rows rows, one wave
+ *   steps_per_launch  T = 1, 2, 4, 5, 6 or 7; T > 1 adds strip tasks (columns
+ *                as for lbm_launch variants 8-13) of seg_rows rows, one wave
  *                each
  *   seg_rows     rows of a strip task, 1 .. 4096
  *   waves        waves per workgroup of the T-step launch, 1 .. 4

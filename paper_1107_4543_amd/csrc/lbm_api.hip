@@ -101,8 +101,8 @@ lbm_launch default_single(const View &)
 
 // Large lattices (>= 2^22 cells): several steps per launch with the shape
 // measured fastest for the storage type on 4096^2 and 8192^2 lattices
-// (variant, waves per workgroup, segment rows, flags): FP32 (12, 4, 176, 2),
-// FP16 (12, 4, 64, 0), BF16 (11, 1, 64, 0), FP64 (11, 4, 176, 12).  Smaller
+// (variant, waves per workgroup, segment rows, flags): FP32 (13, 4, 176, 2),
+// FP16 (12, 4, 64, 0), BF16 (12, 4, 64, 2), FP64 (11, 4, 176, 12).  Smaller
 // lattices offer too few strip segments to keep the GPU busy through the
 // pipeline and keep the one-step shape.
 lbm_launch default_launch(const View &v)
@@ -112,9 +112,9 @@ lbm_launch default_launch(const View &v)
     c.block_x = 64;
     c.xcd_remap = 1;
     switch (v.storage) {
-    case LBM_STORE_F32: c.variant = 12; c.block_y = 4; c.rows = 176; c.flags = 2; break;
+    case LBM_STORE_F32: c.variant = 13; c.block_y = 4; c.rows = 176; c.flags = 2; break;
     case LBM_STORE_F16: c.variant = 12; c.block_y = 4; c.rows = 64; c.flags = 0; break;
-    case LBM_STORE_BF16: c.variant = 11; c.block_y = 1; c.rows = 64; c.flags = 0; break;
+    case LBM_STORE_BF16: c.variant = 12; c.block_y = 4; c.rows = 64; c.flags = 2; break;
     default: c.variant = 11; c.block_y = 4; c.rows = 176; c.flags = 12; break;
     }
     return c;
@@ -162,7 +162,7 @@ std::vector<lbm_launch> variant_candidates(const View &v, const lbm_launch &best
 std::vector<lbm_launch> multi_candidates(const View &v)
 {
     std::vector<lbm_launch> out;
-    for (int var = 8; var <= 12; ++var)
+    for (int var = 8; var <= 13; ++var)
         for (int by : {1, 4})
             for (int rows : {32, 64, 176, 256})
                 for (int flags : {0, 2, 4, 12, 18, 20}) {

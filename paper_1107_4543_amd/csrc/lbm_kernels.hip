@@ -1179,6 +1179,8 @@ hipError_t launch_step_typed(const View &v, const void *src, void *dst, const lb
                         LBM_MULTI(T_, 12) LBM_MULTI(T_, 16) LBM_MULTI(T_, 18) LBM_MULTI(T_, 20) LBM_MULTI(T_, 28)
         LBM_MULTI_E(5)
         LBM_MULTI_E(6)
+        // T = 7: plain pipeline only
+        LBM_MULTI(7, 0) LBM_MULTI(7, 2) LBM_MULTI(7, 4) LBM_MULTI(7, 6) LBM_MULTI(7, 8) LBM_MULTI(7, 12)
 #undef LBM_MULTI_E
 #undef LBM_MULTI_T
 #undef LBM_MULTI
@@ -1304,7 +1306,7 @@ size_t storage_bytes(int32_t storage)
     }
 }
 
-int steps_per_launch(const lbm_launch &cfg) { return cfg.variant >= 8 && cfg.variant <= 12 ? cfg.variant - 6 : 1; }
+int steps_per_launch(const lbm_launch &cfg) { return cfg.variant >= 8 && cfg.variant <= 13 ? cfg.variant - 6 : 1; }
 
 // Output columns of a strip: 64 - 2(T-1) lanes see all their neighbours for
 // T stages.  The count is rounded down to a whole number of 32-byte (else
@@ -1325,9 +1327,10 @@ int multi_strip_cols(int T, int elem_bytes)
 
 bool step_shape_supported(const View &v, const lbm_launch &cfg)
 {
-    if (cfg.variant >= 8 && cfg.variant <= 12) {
+    if (cfg.variant >= 8 && cfg.variant <= 13) {
         // several steps per pass: one wave per strip and segment
-        if (cfg.variant >= 11 && (cfg.flags & 1)) return false;   // T = 5, 6: no non-temporal loads
+        if (cfg.variant >= 11 && (cfg.flags & 1)) return false;   // T = 5, 6, 7: no non-temporal loads
+        if (cfg.variant == 13 && (cfg.flags & 16)) return false;  // T = 7: plain pipeline only
         return cfg.block_x == 64 && cfg.block_y >= 1 && cfg.block_y <= 4 && cfg.rows >= 1 &&
                cfg.rows <= 4096 && (cfg.xcd_remap == 0 || cfg.xcd_remap == 1) && cfg.flags >= 0 &&
                cfg.flags <= 29 && !((cfg.flags & 8) && (cfg.flags & 2)) &&
@@ -1424,6 +1427,7 @@ void *pool_multi_typed(int T, int flags)
     LBM_PM_T(4)
     LBM_PM_T(5)
     LBM_PM_T(6)
+    LBM_PM_T(7)
 #undef LBM_PM_T
 #undef LBM_PM
     return nullptr;

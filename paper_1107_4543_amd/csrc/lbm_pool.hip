@@ -370,7 +370,7 @@ bool valid_shape(const lbm_pool_shape &s)
 {
     const bool multi_ok = s.steps_per_launch == 1 ||
                           ((s.steps_per_launch == 2 || s.steps_per_launch == 4 || s.steps_per_launch == 5 ||
-                            s.steps_per_launch == 6) && s.seg_rows >= 1 &&
+                            s.steps_per_launch == 6 || s.steps_per_launch == 7) && s.seg_rows >= 1 &&
                            s.seg_rows <= 4096 && s.waves >= 1 && s.waves <= 4 &&
                            lbm::pool_multi_kernel(LBM_STORE_F32 * 2 + LBM_COMPUTE_F32, s.steps_per_launch, s.flags));
     return s.tile_cells >= 64 && s.tile_cells <= (1 << 22) && s.block >= 64 && s.block <= 1024 && s.block % 64 == 0 &&
@@ -699,7 +699,7 @@ lbm_status lbm_pool_tune(lbm_pool *pool, int32_t reps, lbm_pool_shape *best, dou
                 }
             }
     // several steps per launch (their left-over steps use the best one-step tiles)
-    for (int T : {2, 4, 5, 6})
+    for (int T : {2, 4, 5, 6, 7})
         for (int seg : {32, 64, 128})
             for (int waves : {1, 4})
                 for (int flags : {0, 2, 12})

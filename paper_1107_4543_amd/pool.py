@@ -64,7 +64,7 @@ class Pool:
     def set_shape(self, tile_cells=256, block=512, grid=65536, graph_steps=256, steps_per_launch=4, seg_rows=32,
                   waves=4, flags=2):
         """steps_per_launch 1 advances every member one step per launch over
-        tiles of about tile_cells cells; 2, 4, 5 or 6 uses strip tasks of the
+        tiles of about tile_cells cells; 2, 4, 5, 6 or 7 uses strip tasks of the
         several-steps-per-pass kernel (seg_rows rows, `waves` waves per
         workgroup, kernel flags 0, 2, 4 or 12 as for Lattice.set_launch)."""
         _lib.lbm_pool_set_shape(self._h, _lib.lbm_pool_shape(tile_cells, block, grid, graph_steps, steps_per_launch,

@@ -117,7 +117,7 @@ def test_create_checks_workspace_and_call_order_without_touching_the_device():
         # launch shapes are validated on the host
         assert _lib.lbm_get_launch(h).block_x > 0
         with pytest.raises(_lib.LbmError):
-            _lib.lbm_set_launch(h, _lib.lbm_launch(13, 64, 4, 1, 1, 0))
+            _lib.lbm_set_launch(h, _lib.lbm_launch(14, 64, 4, 1, 1, 0))
         with pytest.raises(_lib.LbmError):
             _lib.lbm_set_launch(h, _lib.lbm_launch(0, 2048, 1, 1, 1, 0))
         _lib.lbm_set_launch(h, _lib.lbm_launch(2, 64, 4, 2, 0, 0))        # 64 % 4 == 0
@@ -143,9 +143,11 @@ def test_multi_step_shapes_are_validated_and_report_their_steps():
     fake = 1 << 32
     h = _lib.lbm_create(d, fake, _lib.lbm_workspace_bytes(d), 0)
     try:
-        for variant, steps in [(0, 1), (4, 1), (7, 1), (8, 2), (9, 3), (10, 4), (11, 5), (12, 6)]:
+        for variant, steps in [(0, 1), (4, 1), (7, 1), (8, 2), (9, 3), (10, 4), (11, 5), (12, 6), (13, 7), (14, 1)]:
             assert _lib.lbm_steps_per_launch(_lib.lbm_launch(variant, 64, 1, 16, 1, 0)) == steps
         _lib.lbm_set_launch(h, _lib.lbm_launch(10, 64, 2, 64, 1, 28))
+        _lib.lbm_set_launch(h, _lib.lbm_launch(13, 64, 4, 176, 1, 2))
+        assert _lib.lbm_steps_per_launch(_lib.lbm_get_launch(h)) == 7
         _lib.lbm_set_launch(h, _lib.lbm_launch(9, 64, 4, 4096, 0, 7))
         assert _lib.lbm_get_launch(h).variant == 9
         for bad in [(8, 128, 1, 16, 1, 0),      # one wave along x
@@ -159,7 +161,9 @@ def test_multi_step_shapes_are_validated_and_report_their_steps():
                     (10, 64, 1, 16, 1, 10),     # one and two rows ahead together
                     (4, 64, 1, 1, 1, 4),        # bit 2 only for several steps per launch
                     (11, 64, 1, 16, 1, 1),      # T = 5: no non-temporal loads
-                    (13, 64, 1, 16, 1, 0)]:     # no such variant
+                    (13, 64, 1, 16, 1, 3),      # T = 7: no non-temporal loads
+                    (13, 64, 1, 16, 1, 18),     # T = 7: no skewed pipeline
+                    (14, 64, 1, 16, 1, 0)]:     # no such variant
             with pytest.raises(_lib.LbmError):
                 _lib.lbm_set_launch(h, _lib.lbm_launch(*bad))
         assert _lib.lbm_get_launch(h).variant == 9

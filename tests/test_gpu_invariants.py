@@ -102,7 +102,10 @@ def test_all_launch_shapes_give_identical_results(storage):
                    dict(variant=10, block_x=64, block_y=4, rows=1, xcd_remap=1, flags=20),
                    # five and six steps per launch
                    dict(variant=11, block_x=64, block_y=1, rows=176, xcd_remap=1, flags=2),
-                   dict(variant=12, block_x=64, block_y=4, rows=9, xcd_remap=0, flags=28)]:
+                   dict(variant=12, block_x=64, block_y=4, rows=9, xcd_remap=0, flags=28),
+                   # seven steps per launch
+                   dict(variant=13, block_x=64, block_y=2, rows=11, xcd_remap=1, flags=2),
+                   dict(variant=13, block_x=64, block_y=4, rows=176, xcd_remap=0, flags=12)]:
         lat = lattice(nx, ny, s, storage, u0=(0.02, 0.01))
         lat.set_launch(**launch)
         f = lat.init(rho, ux, uy).step(25).populations()
@@ -115,15 +118,16 @@ def test_all_launch_shapes_give_identical_results(storage):
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
 @pytest.mark.parametrize("nx,ny", [(1, 1), (5, 3), (63, 9), (62, 2), (130, 70), (200, 5), (3, 130)])
 def test_several_steps_per_launch_equal_single_steps(storage, nx, ny):
-    # tiny, ragged and single-strip lattices; 7 steps leave 1, 1, 3, 2 and 1
-    # single steps over for T = 2 .. 6
+    # tiny, ragged and single-strip lattices; 7 steps leave 1, 1, 3, 2, 1 and
+    # 0 single steps over for T = 2 .. 7
     rho, ux, uy = fields(nx, ny, 5, (0.02, -0.01))
     s = ll_rates()
     kw = dict(u0=(0.02, -0.01), scale_exp=22 if storage in ("f16", "bf16") else None)
     ref = lattice(nx, ny, s, storage, **kw).init(rho, ux, uy).step(7).populations()
     for variant, rows, flags in [(8, 4, 0), (9, 1, 3), (10, 64, 2), (8, 3, 4), (9, 16, 5), (10, 2, 6),
                                  (10, 1, 12), (9, 5, 9), (8, 64, 13), (10, 3, 16), (9, 64, 18), (10, 2, 22),
-                                 (10, 7, 24), (9, 1, 28), (11, 16, 2), (12, 5, 18), (11, 1, 20), (12, 64, 12)]:
+                                 (10, 7, 24), (9, 1, 28), (11, 16, 2), (12, 5, 18), (11, 1, 20), (12, 64, 12),
+                                 (13, 3, 0), (13, 64, 2), (13, 1, 12), (13, 9, 4)]:
         lat = lattice(nx, ny, s, storage, **kw)
         lat.set_launch(variant=variant, block_x=64, block_y=2, rows=rows, xcd_remap=1, flags=flags)
         assert lat.steps_per_launch == variant - 6

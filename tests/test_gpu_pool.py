@@ -35,15 +35,16 @@ SETS = [[1.64, 1.54, 1.9, 1.98], [1.3, 1.1, 1.7, 1.85], [1.99, 1.962820428, 1.99
 SIZES = [(64, 64), (100, 37), (257, 64), (33, 190), (1, 9), (128, 128)]
 STORES = ["f32", "f16", "f64", "bf16", "f32", "f32"]
 STEPS = [37, 100, 0, 64, 5, 91]
-# one step per launch, and T-step strip tasks (T = 2, 4, 5, 6) with their
+# one step per launch, and T-step strip tasks (T = 2, 4, 5, 6, 7) with their
 # one-step launches for left-over steps; with graph_steps 16 the recorded
-# loops are T 2^m steps (16, 10 or 12) and powers of two below T, recorded
+# loops are T 2^m steps (16, 10, 12 or 14) and powers of two below T, recorded
 # with and without one-step launches as the members' counts require
 SCHEDULES = [dict(steps_per_launch=1), dict(steps_per_launch=2, seg_rows=16, waves=2, flags=0),
              dict(steps_per_launch=4, seg_rows=32, waves=4, flags=2),
              dict(steps_per_launch=4, seg_rows=7, waves=1, flags=12),
              dict(steps_per_launch=5, seg_rows=16, waves=4, flags=2),
-             dict(steps_per_launch=6, seg_rows=9, waves=2, flags=0)]
+             dict(steps_per_launch=6, seg_rows=9, waves=2, flags=0),
+             dict(steps_per_launch=7, seg_rows=13, waves=4, flags=2)]
 
 
 @pytest.mark.parametrize("sched", SCHEDULES)
