@@ -336,7 +336,7 @@ def bench_pulses8192(args):
             e_inf = float(d.abs().max()) / A
             e_l2 = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(rho_ref - 1.0))
         spl = lat.steps_per_launch
-        launches = T // spl + T % spl
+        launches = lat.launches_for(T)
         # every launch reads and writes all nine planes once, whether it
         # advances one step or several
         bpl = 18 * STORE_BYTES[storage] * launches / T
@@ -439,7 +439,7 @@ def main():
     # the intermediate rows in registers) and reads and writes every
     # population once: 2 * 9 * sizeof(storage) bytes per cell and launch
     spl = lat.steps_per_launch
-    launches = args.steps // spl + args.steps % spl
+    launches = lat.launches_for(args.steps)             # T-step launches and the left-over one(s)
     us_per_launch = 1e3 * ms / launches
     alg_bytes = 2 * 9 * STORE_BYTES[args.storage] * cells
     achieved = alg_bytes / (us_per_launch * 1e-6) / 1e9

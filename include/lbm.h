@@ -121,8 +121,9 @@ typedef struct lbm_lattice lbm_lattice;
  *             `rows` rows; T = 5, 6 and 7 take no non-temporal loads, T = 7 no
  *             skewed pipeline; block_x must be 64,
  *             block_y (waves per workgroup) 1..4, rows 1..4096.  lbm_step(n)
- *             then makes n / T such launches and n % T one-step launches
- *             (with the one-step shape last set or found by lbm_tune).
+ *             then makes n / T such launches and takes the remaining steps
+ *             as described there (one-step launches use the one-step shape
+ *             last set or found by lbm_tune).
  *   block_x   lanes along x per workgroup, block_y rows per workgroup pass;
  *             64 <= block_x * block_y <= 1024
  *   rows      rows each lane processes, 1..64 (tile height = block_y * rows)
@@ -191,8 +192,15 @@ LBM_API lbm_status lbm_init_equilibrium(lbm_lattice *lat, const double *rho, con
 
 /* Advances n >= 0 steps of the fused collide-and-pull-stream update
  * (Sec. 2.1, Eq. blbs with Lambda = M^{-1} S M; pull form of Sec. 2.2, Eq.
- * l-mrt-lbs).  Enqueued.  LBM_E_STATE before init. */
+ * l-mrt-lbs).  Enqueued.  LBM_E_STATE before init.  With a shape of T > 1
+ * steps per launch: n / T launches of it, then the r = n % T remaining
+ * steps in one launch of the same shape with r steps per pass (variant
+ * 6 + r) when r >= 2 and that shape is supported, else r one-step
+ * launches; every split gives bit-identical results. */
 LBM_API lbm_status lbm_step(lbm_lattice *lat, int64_t n);
+/* Kernel launches lbm_step(lat, n) makes with the current shapes; -1 if
+ * lat is NULL or n < 0. */
+LBM_API int64_t lbm_step_launches(const lbm_lattice *lat, int64_t n);
 
 /* Macroscopic fields of the current state (Sec. 2.1, Eq. q-macro):
  * rho = sum_i f_i, u = (sum_i v_i f_i) / rho, evaluated in FP64.
@@ -311,7 +319,8 @@ typedef struct lbm_pool_shape {
 LBM_API size_t lbm_pool_workspace_bytes(int32_t max_members, int32_t max_tiles);
 /* Creates a pool.  dev_ws: device pointer, 256-byte aligned, at least
  * lbm_pool_workspace_bytes bytes, owned by the caller; stream: the pool's
- * hipStream_t.  Allocates pinned host staging for the tables. */
+ * hipStream_t.  Allocates pinned host staging for the tables.  Initial
+ * shape {256, 512, 4096, 256, 7, 32, 4, 12} (seven steps per launch). */
 LBM_API lbm_status lbm_pool_create(void *dev_ws, size_t ws_bytes, void *stream, int32_t max_members,
                                    int32_t max_tiles, lbm_pool **out);
 /* Returns every member to its lattice (as lbm_pool_remove) and frees the

@@ -91,6 +91,7 @@ SIGNATURES = {
     "lbm_tune": (_st, [_vp, ctypes.c_int32, ctypes.POINTER(lbm_launch), _dp]),
     "lbm_time_launches": (_st, [_vp, ctypes.c_int32, _dp]),
     "lbm_steps_per_launch": (ctypes.c_int32, [ctypes.c_void_p]),
+    "lbm_step_launches": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_int64]),
     "lbm_pool_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "lbm_pool_create": (_st, [_vp, ctypes.c_size_t, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_vp)]),
     "lbm_pool_destroy": (_st, [_vp]),
@@ -249,6 +250,10 @@ def lbm_time_launches(h, n):
 
 def lbm_steps_per_launch(cfg):
     return int(load().lbm_steps_per_launch(ctypes.byref(cfg)))
+
+
+def lbm_step_launches(h, n):
+    return int(load().lbm_step_launches(h, int(n)))
 
 
 # ---- pools ----------------------------------------------------------------------

@@ -347,25 +347,55 @@ lbm_status lbm_init_equilibrium(lbm_lattice *lat, const double *rho, const doubl
     return LBM_OK;
 }
 
+namespace {
+
+// The r < T steps left after the T-step launches of lbm_step: one launch of
+// the current shape with r steps per pass when r >= 2 and that shape is
+// supported (*ok), else r one-step launches.
+lbm_launch remainder_shape(const lbm_lattice *lat, int r, bool *ok)
+{
+    lbm_launch c = lat->launch;
+    c.variant = 6 + r;
+    *ok = r >= 2 && lbm::steps_per_launch(lat->launch) > r && lbm::step_shape_supported(lat->v, c);
+    return c;
+}
+
+}  // namespace
+
 lbm_status lbm_step(lbm_lattice *lat, int64_t n)
 {
     if (!lat) return fail(LBM_E_INVAL, "lattice is NULL");
     if (n < 0) return fail(LBM_E_INVAL, "n must be >= 0");
     if (!lat->initialized) return fail(LBM_E_STATE, "lbm_step before lbm_init_equilibrium");
     if (lat->pool) return busy(lat);
-    // a shape that advances T steps per launch takes n / T launches; the
-    // remaining n % T steps use the one-step shape
     const int T = lbm::steps_per_launch(lat->launch);
-    for (int64_t k = 0; k < n;) {
-        const bool multi = n - k >= T;
-        const lbm_launch &c = multi ? lat->launch : lat->single;
+    auto launch = [&](const lbm_launch &c, int steps) -> lbm_status {
         hipError_t e = lbm::launch_step(lat->v, lat->buf[lat->cur], lat->buf[lat->cur ^ 1], c, lat->stream);
         if (e != hipSuccess) return hip_fail(e, "step launch");
         lat->cur ^= 1;
-        lat->t += multi ? T : 1;
-        k += multi ? T : 1;
-    }
+        lat->t += steps;
+        return LBM_OK;
+    };
+    lbm_status st;
+    for (int64_t k = 0; k < n / T; ++k)
+        if ((st = launch(lat->launch, T)) != LBM_OK) return st;
+    const int r = (int)(n % T);
+    bool ok;
+    const lbm_launch rest = remainder_shape(lat, r, &ok);
+    if (ok) return launch(rest, r);
+    for (int k = 0; k < r; ++k)
+        if ((st = launch(lat->single, 1)) != LBM_OK) return st;
     return LBM_OK;
+}
+
+int64_t lbm_step_launches(const lbm_lattice *lat, int64_t n)
+{
+    if (!lat || n < 0) return -1;
+    const int T = lbm::steps_per_launch(lat->launch);
+    const int r = (int)(n % T);
+    bool ok;
+    (void)remainder_shape(lat, r, &ok);
+    return n / T + (ok ? 1 : r);
 }
 
 lbm_status lbm_read_moments(lbm_lattice *lat, double *rho, double *ux, double *uy)

@@ -76,7 +76,7 @@ struct lbm_pool {
     int ntiles = 0;
     int max_class_tiles = 0;         // largest one-step tile range of one class
     int max_class_tasks = 0;         // largest T-step task range of one class
-    lbm_pool_shape shape{256, 512, 65536, 256, 4, 32, 4, 2};
+    lbm_pool_shape shape{256, 512, 4096, 256, 7, 32, 4, 12};
     std::vector<Slot> slots;
     std::vector<int> finishing;      // slot indices in completion order
     std::map<std::tuple<unsigned, int, int, int, int>, GraphEntry> graphs;   // (class mask, steps, one-step launches, grids)

@@ -156,6 +156,10 @@ class Lattice:
         """Steps one launch of the current shape advances."""
         return _lib.lbm_steps_per_launch(_lib.lbm_get_launch(self._h))
 
+    def launches_for(self, n):
+        """Kernel launches step(n) makes with the current shapes."""
+        return _lib.lbm_step_launches(self._h, n)
+
     def tune(self, reps=10):
         """Selects the launch shape with the least time per step; returns
         (shape, microseconds per step)."""

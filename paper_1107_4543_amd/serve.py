@@ -99,7 +99,7 @@ class Server:
         self.device = torch.device(device)
         self.budget = int(hbm_budget_bytes)
         self.pool = Pool(max_members=max_members, max_tiles=max_tiles, device=self.device)
-        self.pool.set_shape(tile_cells=tile_cells, block=512, grid=65536, graph_steps=256)
+        self.pool.set_shape(tile_cells=tile_cells, block=512, grid=4096, graph_steps=256)
         self.max_members = max_members
         self.chunk_ms = chunk_ms
         self.policy = policy

@@ -171,6 +171,25 @@ def test_multi_step_shapes_are_validated_and_report_their_steps():
         _lib.lbm_destroy(h)
 
 
+def test_step_launch_counts_follow_the_remainder_rule():
+    fake = 1 << 32
+    d = desc(nx=66)
+    h = _lib.lbm_create(d, fake, _lib.lbm_workspace_bytes(d), 0)
+    try:
+        assert _lib.lbm_step_launches(None, 5) == -1 and _lib.lbm_step_launches(h, -1) == -1
+        _lib.lbm_set_launch(h, _lib.lbm_launch(13, 64, 4, 176, 1, 2))          # T = 7
+        for n, want in [(0, 0), (1, 1), (2, 1), (6, 1), (7, 1), (8, 2), (9, 2), (12, 2), (2000, 286)]:
+            assert _lib.lbm_step_launches(h, n) == want, n
+        _lib.lbm_set_launch(h, _lib.lbm_launch(10, 64, 2, 64, 1, 18))          # T = 4, skewed
+        # 2 left over: a two-step pass cannot be skewed, so two one-step launches
+        assert _lib.lbm_step_launches(h, 6) == 3
+        assert _lib.lbm_step_launches(h, 7) == 2                               # 3 left: skewed T = 3
+        _lib.lbm_set_launch(h, _lib.lbm_launch(0, 64, 4, 1, 1, 0))
+        assert _lib.lbm_step_launches(h, 9) == 9
+    finally:
+        _lib.lbm_destroy(h)
+
+
 def test_status_strings():
     for s in (0, -1, -2, -3, -4, -5, 42):
         assert isinstance(_lib.lbm_status_string(s), str) and _lib.lbm_status_string(s)

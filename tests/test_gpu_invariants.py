@@ -136,6 +136,24 @@ def test_several_steps_per_launch_equal_single_steps(storage, nx, ny):
         assert torch.equal(lat.populations(), ref), (variant, rows, flags)
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_left_over_steps_take_one_shorter_pass(storage):
+    # with T = 7, n = 7q + r: q passes, then one r-step pass (r >= 2) or one
+    # one-step launch; every split equals n single steps bitwise
+    nx, ny = 140, 90
+    rho, ux, uy = fields(nx, ny, 6, (0.03, 0.0))
+    s = ll_rates()
+    kw = dict(u0=(0.03, 0.0), scale_exp=22 if storage == "f16" else None)
+    for n in (2, 8, 9, 12, 13, 20):
+        ref = lattice(nx, ny, s, storage, **kw).init(rho, ux, uy).step(n).populations()
+        lat = lattice(nx, ny, s, storage, **kw)
+        lat.set_launch(variant=13, block_x=64, block_y=2, rows=32, xcd_remap=1, flags=2)
+        assert lat.launches_for(n) == n // 7 + (1 if n % 7 != 0 else 0)
+        lat.init(rho, ux, uy).step(n)
+        assert lat.t == n
+        assert torch.equal(lat.populations(), ref), n
+
+
 def test_tune_and_timing_leave_the_state_unchanged():
     nx, ny = 512, 128
     rho, ux, uy = fields(nx, ny, 4)
