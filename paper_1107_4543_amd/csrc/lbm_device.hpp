@@ -87,9 +87,17 @@ __host__ __device__ __forceinline__ void back_transform(const T m[9], T f[9])
 __device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// 1/x: the hardware reciprocal (about 1 ulp) in FP32, an IEEE division in FP64.
+// 1/x: the hardware reciprocal (about 1 ulp) in FP32; in FP64 the hardware
+// estimate refined by two Newton-Raphson steps r <- r + r (1 - x r), each
+// of which squares the relative error (x is a density near rho0: positive
+// and normal, so the special cases of a full division do not arise).
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
 
 // The collision increment dg = g* - g of one cell in the compute type T.
 //
@@ -110,7 +118,9 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 //     N_Q = ax + ay - Q0 rho',  N_P = ax - ay - P0 rho',  ax = jx (t jx + 2 j0x)
 //     N_X = jy (t jx + j0x) + j0y jx - X0 rho'
 // (the same quantities as the equilibrium above, in fewer operations; the
-// kinetic moments e, eps, q are never formed).
+// kinetic moments e, eps, q are never formed).  The q terms enter M^T a
+// through lam_q directly (dg_1 = A + lam_pxx - 2 lam_q x_5, dg_5 = B + lam_pxy
+// + lam_q (x_5 + x_6), ...).
 template <typename T>
 __device__ __forceinline__ void collide_increment(const T g[9], const Relax<T> &r, T t, T dg[9])
 {
@@ -137,8 +147,8 @@ __device__ __forceinline__ void collide_increment(const T g[9], const Relax<T> &
     // relaxation terms a_k, k = 3..8
     const T a3 = r.lam_e * fmad(nQ, T(3) * inv, fmad(T(-4), b, fmad(T(2), g[0], -a)));
     const T a4 = (T(3) * r.lam_eps) * fmad(-nQ, inv, a - g[0]);
-    const T a5 = r.lam_q * fmad(T(-2), dxd, dx1);
-    const T a6 = r.lam_q * fmad(T(-2), dyd, dy1);
+    const T x5 = fmad(T(-2), dxd, dx1);
+    const T x6 = fmad(T(-2), dyd, dy1);
     const T x7 = fmad(nP, inv, -pxx);
     const T x8 = fmad(nX, inv, -pxy);
     // dg = M^T a
@@ -146,16 +156,17 @@ __device__ __forceinline__ void collide_increment(const T g[9], const Relax<T> &
     const T B = fmad(T(2), a3, a4);
     const T A7 = fmad(r.lam_nu, x7, A), Am7 = fmad(-r.lam_nu, x7, A);
     const T B8 = fmad(r.lam_nu, x8, B), Bm8 = fmad(-r.lam_nu, x8, B);
-    const T p56 = a5 + a6, m56 = a5 - a6;
+    const T q2 = T(2) * r.lam_q;
+    const T s56 = x5 + x6, d56 = x5 - x6;
     dg[0] = T(4) * (a4 - a3);
-    dg[1] = fmad(T(-2), a5, A7);
-    dg[2] = fmad(T(-2), a6, Am7);
-    dg[3] = fmad(T(2), a5, A7);
-    dg[4] = fmad(T(2), a6, Am7);
-    dg[5] = B8 + p56;
-    dg[6] = Bm8 - m56;
-    dg[7] = B8 - p56;
-    dg[8] = Bm8 + m56;
+    dg[1] = fmad(-q2, x5, A7);
+    dg[2] = fmad(-q2, x6, Am7);
+    dg[3] = fmad(q2, x5, A7);
+    dg[4] = fmad(q2, x6, Am7);
+    dg[5] = fmad(r.lam_q, s56, B8);
+    dg[6] = fmad(-r.lam_q, d56, Bm8);
+    dg[7] = fmad(-r.lam_q, s56, B8);
+    dg[8] = fmad(r.lam_q, d56, Bm8);
 }
 
 // ---- storage types ---------------------------------------------------------

@@ -64,7 +64,12 @@ __device__ __forceinline__ int remap_xcd(int bid, int nb)
 }
 
 // Collide one cell held as widened stored values w (in place).  16-bit
-// storage is collided in its scaled units (see collide_increment).
+// storage is collided in its scaled units (see collide_increment).  The
+// last operation before a value is rounded to its storage type is the add
+// of the increment: a fused multiply-add there could be merged with a
+// 16-bit conversion into one mixed-precision instruction that rounds once
+// instead of twice, and kernels that got it would no longer agree bitwise
+// with those that did not.
 template <typename S, typename C>
 __device__ __forceinline__ void cell_update(typename Store<S>::wide w[9], const Relax<C> &r,
                                             float /*scale*/, float inv_scale)
