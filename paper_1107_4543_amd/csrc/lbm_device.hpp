@@ -215,14 +215,8 @@ struct Store<bf16_tag> {
     using wide = float;
     static constexpr bool scaled = true;
     __device__ static __forceinline__ float widen(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
-    __device__ static __forceinline__ uint16_t narrow(float v)
-    {
-        uint32_t u = __float_as_uint(v);
-        if ((u & 0x7fffffffu) > 0x7f800000u)             // NaN stays a quiet NaN
-            return (uint16_t)((u >> 16) | 0x0040u);
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return (uint16_t)(u >> 16);
-    }
+    // the hardware conversion (round to nearest even; NaN stays NaN)
+    __device__ static __forceinline__ uint16_t narrow(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 };
 
 // N consecutive raw values as one naturally aligned vector (one wide load or
