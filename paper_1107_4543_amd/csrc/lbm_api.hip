@@ -350,13 +350,14 @@ lbm_status lbm_init_equilibrium(lbm_lattice *lat, const double *rho, const doubl
 namespace {
 
 // The r < T steps left after the T-step launches of lbm_step: one launch of
-// the current shape with r steps per pass when r >= 2 and that shape is
-// supported (*ok), else r one-step launches.
+// the current shape with r steps per pass when r >= 2 (then T > 2 and the
+// current shape is a several-steps one) and that shape is supported (*ok),
+// else r one-step launches.
 lbm_launch remainder_shape(const lbm_lattice *lat, int r, bool *ok)
 {
     lbm_launch c = lat->launch;
     c.variant = 6 + r;
-    *ok = r >= 2 && lbm::steps_per_launch(lat->launch) > r && lbm::step_shape_supported(lat->v, c);
+    *ok = r >= 2 && lbm::step_shape_supported(lat->v, c);
     return c;
 }
 
