@@ -12,13 +12,15 @@ The inputs are resident in HBM before timing starts; the timed region is K
 consecutive steps on the lattice's stream, bracketed by device
 synchronisation and HIP events.
 
-Prints one JSON line: MLUPS, the roofline of the step kernel (algorithmic
-bytes 2 * 9 * sizeof(storage) per cell and launch -- every launch reads and
-writes each population once, however many steps it advances -- over its
-measured average duration, against the 8 TB/s HBM peak), measured HBM traffic from the
-committed rocprofv3 counter summary when it matches the current kernel
-source, and the FP64 CPU oracle timed on a bounded sample of the same
-workload on the host cores.
+Prints one JSON line: MLUPS, the roofline of the step kernel over its
+measured average launch duration -- for one step per launch the HBM bound
+(algorithmic bytes 2 * 9 * sizeof(storage) per cell and launch against the
+8 TB/s peak); for several steps per launch the vector-ALU bound (the
+collision's 71 algorithmic operations per cell and step against the
+non-packed issue peak), with the HBM figures beside it -- measured HBM
+traffic from the committed rocprofv3 counter summary when it matches the
+current kernel source, and the FP64 CPU oracle timed on a bounded sample of
+the same workload on the host cores.
 """
 import argparse
 import hashlib
@@ -49,6 +51,15 @@ def kernel_source_hash():
 
 
 VALU_PEAK = 256 * 4 * 16 * 2.4e9      # VALU lane-instructions per second (non-packed)
+# Arithmetic of one lattice update in the compute type: the folded collision's
+# 70 additions, multiplications and fused multiply-adds plus its reciprocal
+# (the moment sums, equilibrium numerators, relaxation, M^T and the
+# increment; the kernels' comments list them).  Vector-ALU peaks in
+# operations per second: one operation per lane and clock on 256 CUs x 4
+# SIMDs x 16 lanes at 2.4 GHz in FP32 (packed FP32 is not used), half that in
+# FP64.
+ALG_OPS_PER_LU = 71
+ALU_PEAK = {"f32": 256 * 4 * 16 * 2.4e9, "f64": 256 * 4 * 16 * 2.4e9 / 2}
 
 
 def read_profile(workload, storage, launch):
@@ -150,6 +161,26 @@ def copy_probe(nbytes, reps):
             "GBps": round(2 * nbytes / (us * 1e-6) / 1e9, 1)}
 
 
+def pool_roofline(T, cells, launches, ms):
+    """Roofline of the pool's step kernel over a timed pass: HBM for one step
+    per launch, the vector ALU (algorithmic operations, FP32) for T > 1."""
+    us = 1e3 * ms / launches
+    gbps = 72 * cells / (us * 1e-6) / 1e9
+    hbm = {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+           "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": None, "algorithmic_bytes_per_launch": 72 * cells}
+    common = {"kernel": ("k_pool_multi (%d steps per launch, persistent, per storage class)" % T if T > 1
+                         else "k_pool_step (persistent, per storage class)"),
+              "steps_per_launch": T, "launches": launches, "avg_launch_us": round(us, 3)}
+    if T == 1:
+        return dict(hbm, **common)
+    ops = ALG_OPS_PER_LU * cells * T
+    tops = ops / (us * 1e-6) / 1e12
+    peak = ALU_PEAK["f32"] / 1e12
+    return dict({"bound": "alu", "achieved": round(tops, 2), "peak": round(peak, 2), "unit": "T F32 ops/s",
+                 "frac": round(tops / peak, 4), "traffic": None, "algorithmic_ops_per_launch": ops,
+                 "ops_per_update": ALG_OPS_PER_LU, "hbm": hbm}, **common)
+
+
 def bench_batch256(args):
     """256 independent lattices (sides log-uniform in [64, 1024], sampled
     stable rates, one pulse each, FP32, 500 steps): the whole job in one pool
@@ -243,14 +274,7 @@ def bench_batch256(args):
         "config": {"workload": "batch256", "lattices": len(specs), "cells": cells, "steps": steps,
                    "seed": w["seed"], "pool_shape": shape, "stability_draws": draws[0],
                    "stability_acceptance": round(len(specs) / draws[0], 4)},
-        "roofline": {"bound": "hbm", "achieved": round(alg / (ms_batched / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(alg / (ms_batched / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
-                     "traffic": None,
-                     "kernel": ("k_pool_multi (%d steps per launch, persistent, per storage class)" % T if T > 1
-                                else "k_pool_step (persistent, per storage class)"),
-                     "algorithmic_bytes_per_launch": 72 * cells, "steps_per_launch": T,
-                     "launches": member_launches,
-                     "avg_launch_us": round(1e3 * ms_batched / member_launches, 3)},
+        "roofline": pool_roofline(T, cells, member_launches, ms_batched),
         "sequential_plain": {"value": round(lups / (ms_seq / 1e3) / 1e6, 1), "unit": "MLUPS",
                              "ms": round(ms_seq, 2), "launches": len(specs) * steps,
                              "launch_shape": lats[0].launch},
@@ -341,7 +365,10 @@ def bench_pulses8192(args):
         # advances one step or several
         bpl = 18 * STORE_BYTES[storage] * launches / T
         gbps = 18 * STORE_BYTES[storage] * nx * ny * launches / (ms / 1e3) / 1e9
-        rows.append({"storage": storage, "compute": compute, "mlups": round(nx * ny * T / (ms / 1e3) / 1e6, 1),
+        mlups_r = nx * ny * T / (ms / 1e3) / 1e6
+        alu_tops = ALG_OPS_PER_LU * mlups_r * 1e6 / 1e12
+        rows.append({"storage": storage, "compute": compute, "mlups": round(mlups_r, 1),
+                     "alg_ops_TOPs": round(alu_tops, 2), "alu_frac": round(alu_tops * 1e12 / ALU_PEAK[compute], 4),
                      "bytes_per_lu": round(bpl, 3), "achieved_GBps": round(gbps, 1),
                      "frac": round(gbps / HBM_PEAK_GBPS, 4), "launch": launch, "steps_per_launch": spl,
                      "scale_exp": lat.scale_exp,
@@ -450,23 +477,37 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.storage, "data": "synthetic", "config": cfg,
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                     "kernel": ("k_step_multi (%d steps per pass)" % spl if spl > 1
-                                else "k_step (fused collide + pull stream)"),
-                     "algorithmic_bytes_per_launch": alg_bytes, "steps_per_launch": spl,
-                     "launches": launches, "avg_launch_us": round(us_per_launch, 3)},
     }
-    kv = read_profile("waves4096", args.storage, lat.launch)
-    if kv and "valu_lane_instructions_per_update" in kv:
-        # the kernel moves a quarter of the one-step bytes per update, so its
-        # limit is instruction issue: VALU lane-instructions per update (from
-        # the compiled loop, see the profile) times updates per second
-        per_lu = float(kv["valu_lane_instructions_per_update"])
-        out["roofline"]["valu_issue"] = {"lane_instructions_per_update": per_lu,
-                                         "achieved": round(per_lu * mlups * 1e6 / 1e12, 2),
-                                         "peak": round(VALU_PEAK / 1e12, 2), "unit": "T lane-instr/s",
-                                         "frac": round(per_lu * mlups * 1e6 / VALU_PEAK, 4)}
+    hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+           "algorithmic_bytes_per_launch": alg_bytes}
+    common = {"kernel": ("k_step_multi (%d steps per pass)" % spl if spl > 1
+                         else "k_step (fused collide + pull stream)"),
+              "steps_per_launch": spl, "launches": launches, "avg_launch_us": round(us_per_launch, 3)}
+    if spl == 1:
+        # one step per launch: every update reads and writes all nine planes
+        out["roofline"] = dict(hbm, **common)
+    else:
+        # several steps per launch move a T-th of the bytes per update; the
+        # bound is the vector ALU: algorithmic operations per launch over the
+        # launch time, against the non-packed issue peak of the compute type
+        compute = lat.compute
+        ops = ALG_OPS_PER_LU * cells * spl
+        tops = ops / (us_per_launch * 1e-6) / 1e12
+        peak = ALU_PEAK[compute] / 1e12
+        out["roofline"] = dict({"bound": "alu", "achieved": round(tops, 2), "peak": round(peak, 2),
+                                "unit": "T %s ops/s" % compute.upper(), "frac": round(tops / peak, 4),
+                                "traffic": traffic, "algorithmic_ops_per_launch": ops,
+                                "ops_per_update": ALG_OPS_PER_LU, "hbm": hbm}, **common)
+        kv = read_profile("waves4096", args.storage, lat.launch)
+        if kv and "valu_lane_instructions_per_update" in kv:
+            # what the compiled loop issues per useful update (halo lanes,
+            # prologue rows and register moves included), see the profile
+            per_lu = float(kv["valu_lane_instructions_per_update"])
+            out["roofline"]["valu_issue"] = {"lane_instructions_per_update": per_lu,
+                                             "achieved": round(per_lu * mlups * 1e6 / 1e12, 2),
+                                             "peak": round(VALU_PEAK / 1e12, 2), "unit": "T lane-instr/s",
+                                             "frac": round(per_lu * mlups * 1e6 / VALU_PEAK, 4)}
     out["context"] = {"copy_probe": copy_probe(alg_bytes // 2, 10), "device": torch.cuda.get_device_name(0)}
     if args.cpu_budget > 0:
         out["cpu_baseline"] = cpu_baseline(rates, fields1, lat.nx, lat.ny, w["u0x"], args.cpu_budget)
