@@ -101,7 +101,7 @@ lbm_launch default_single(const View &)
 
 // Large lattices (>= 2^22 cells): several steps per launch with the shape
 // measured fastest for the storage type on 4096^2 and 8192^2 lattices
-// (variant, waves per workgroup, segment rows, flags): FP32 (13, 4, 176, 2),
+// (variant, waves per workgroup, segment rows, flags): FP32 (13, 4, 168, 2),
 // FP16 (11, 4, 64, 12), BF16 (11, 4, 64, 8), FP64 (11, 4, 176, 12).  Smaller
 // lattices offer too few strip segments to keep the GPU busy through the
 // pipeline and keep the one-step shape.
@@ -112,7 +112,7 @@ lbm_launch default_launch(const View &v)
     c.block_x = 64;
     c.xcd_remap = 1;
     switch (v.storage) {
-    case LBM_STORE_F32: c.variant = 13; c.block_y = 4; c.rows = 176; c.flags = 2; break;
+    case LBM_STORE_F32: c.variant = 13; c.block_y = 4; c.rows = 168; c.flags = 2; break;
     case LBM_STORE_F16: c.variant = 11; c.block_y = 4; c.rows = 64; c.flags = 12; break;
     case LBM_STORE_BF16: c.variant = 11; c.block_y = 4; c.rows = 64; c.flags = 8; break;
     default: c.variant = 11; c.block_y = 4; c.rows = 176; c.flags = 12; break;
@@ -164,7 +164,7 @@ std::vector<lbm_launch> multi_candidates(const View &v)
     std::vector<lbm_launch> out;
     for (int var = 8; var <= 13; ++var)
         for (int by : {1, 4})
-            for (int rows : {32, 64, 176, 256})
+            for (int rows : {32, 64, 168, 176, 256})
                 for (int flags : {0, 2, 4, 12, 18, 20}) {
                     lbm_launch c{};
                     c.variant = var;
