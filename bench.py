@@ -96,7 +96,7 @@ def read_traffic(workload, storage, launch):
 # Launch shapes lbm_tune selected for the 4096^2 wave workload on MI355X
 # (variants 11, 12 and 13: five, six and seven steps per pass); --tune searches again.
 DEFAULT_LAUNCH = {"f32": "13,64,4,168,1,2", "f16": "11,64,4,64,1,12", "bf16": "11,64,4,64,1,8",
-                  "f64": "11,64,4,176,1,12"}
+                  "f64": "13,64,4,168,1,12"}
 
 
 def build_waves4096(storage):

@@ -103,7 +103,7 @@ typedef struct lbm_lattice lbm_lattice;
 /* Launch shape of the fused step kernel (chosen by lbm_tune or set by hand;
  * a new lattice of at least 2^22 cells starts with a several-steps shape
  * by storage type: FP32 {13, 64, 4, 168, 1, 2}, FP16 {11, 64, 4, 64, 1, 12},
- * BF16 {11, 64, 4, 64, 1, 8}, FP64 {11, 64, 4, 176, 1, 12}; a smaller one
+ * BF16 {11, 64, 4, 64, 1, 8}, FP64 {13, 64, 4, 168, 1, 12}; a smaller one
  * with {0, 64, 4, 1, 1, 0}).
  *   variant   0 = one cell per lane (nine direct loads),
  *             1, 2, 3 = 2, 4, 8 consecutive cells per lane (aligned vector

@@ -102,7 +102,7 @@ lbm_launch default_single(const View &)
 // Large lattices (>= 2^22 cells): several steps per launch with the shape
 // measured fastest for the storage type on 4096^2 and 8192^2 lattices
 // (variant, waves per workgroup, segment rows, flags): FP32 (13, 4, 168, 2),
-// FP16 (11, 4, 64, 12), BF16 (11, 4, 64, 8), FP64 (11, 4, 176, 12).  Smaller
+// FP16 (11, 4, 64, 12), BF16 (11, 4, 64, 8), FP64 (13, 4, 168, 12).  Smaller
 // lattices offer too few strip segments to keep the GPU busy through the
 // pipeline and keep the one-step shape.
 lbm_launch default_launch(const View &v)
@@ -115,7 +115,7 @@ lbm_launch default_launch(const View &v)
     case LBM_STORE_F32: c.variant = 13; c.block_y = 4; c.rows = 168; c.flags = 2; break;
     case LBM_STORE_F16: c.variant = 11; c.block_y = 4; c.rows = 64; c.flags = 12; break;
     case LBM_STORE_BF16: c.variant = 11; c.block_y = 4; c.rows = 64; c.flags = 8; break;
-    default: c.variant = 11; c.block_y = 4; c.rows = 176; c.flags = 12; break;
+    default: c.variant = 13; c.block_y = 4; c.rows = 168; c.flags = 12; break;
     }
     return c;
 }

@@ -53,3 +53,20 @@ def test_profile_lookup_checks_kernel_and_source():
     assert bench.read_traffic("waves4096", "f32", other) is None
     assert bench.read_traffic("waves4096", "f16", launch) is None or os.path.exists(
         os.path.join(ROOT, "profiles", "traffic_step_multi_f16_waves4096.txt"))
+
+
+def test_pool_roofline_bound_follows_the_steps_per_launch():
+    cells, launches, ms = 1 << 20, 10, 2.0
+    one = bench.pool_roofline(1, cells, launches, ms)
+    assert one["bound"] == "hbm" and one["unit"] == "GB/s"
+    us = 1e3 * ms / launches
+    assert abs(one["achieved"] - 72 * cells / (us * 1e-6) / 1e9) < 0.1
+    assert abs(one["frac"] - one["achieved"] / bench.HBM_PEAK_GBPS) < 1e-4
+    multi = bench.pool_roofline(7, cells, launches, ms)
+    assert multi["bound"] == "alu" and multi["ops_per_update"] == bench.ALG_OPS_PER_LU
+    assert multi["algorithmic_ops_per_launch"] == bench.ALG_OPS_PER_LU * cells * 7
+    assert abs(multi["achieved"] - bench.ALG_OPS_PER_LU * cells * 7 / (us * 1e-6) / 1e12) < 0.01
+    assert abs(multi["peak"] - 39.32) < 0.01 and 0 < multi["frac"] < 1
+    assert multi["hbm"]["achieved"] == one["achieved"]
+    # the FP64 vector peak is half the FP32 one
+    assert bench.ALU_PEAK["f64"] * 2 == bench.ALU_PEAK["f32"]
