@@ -130,7 +130,7 @@ typedef struct lbm_lattice lbm_lattice;
  *   xcd_remap 1 = renumber workgroups so that neighbouring tiles run on the
  *             same XCD (shared L2), 0 = hardware order
  *   flags     bit 0: non-temporal loads; bit 1: issue the next row's (variants
- *             0, 8, 9, 10) or next chunk's (variant 4) loads before colliding
+ *             0 and 8-13) or next chunk's (variant 4) loads before colliding
  *             the current cells (variants 0, 4, 8-13 only); bit 2
  *             (variants 8-13 only): move values between neighbouring
  *             lanes with DPP whole-wave shifts instead of LDS shuffles; bit 3
@@ -251,7 +251,8 @@ LBM_API lbm_status lbm_get_launch(const lbm_lattice *lat, lbm_launch *out);
 LBM_API lbm_status lbm_set_launch(lbm_lattice *lat, const lbm_launch *cfg);
 /* Times the supported launch shapes on this lattice (reps launches each,
  * the state is left unchanged) and selects the one with the least time per
- * step; the fastest one-step shape is kept for left-over steps.  best_us
+ * step; the fastest one-step shape is kept for a single left-over step
+ * (see lbm_step for the rest).  best_us
  * receives microseconds per step.  best/best_us may be NULL.  Syncs. */
 LBM_API lbm_status lbm_tune(lbm_lattice *lat, int32_t reps, lbm_launch *best, double *best_us);
 /* Times n launches of the current shape (state unchanged; syncs); avg_us is
