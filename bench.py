@@ -254,17 +254,25 @@ def bench_batch256(args):
 
     lups = cells * steps
     # each member reads and writes its nine planes once per launch it takes;
-    # replay the pool's chunking (loops of T 2^m steps, powers of two below
-    # T) to count its T-step and one-step launches
+    # replay the pool's chunking (loops of T 2^m steps, then the remaining
+    # r < T steps as one pass) to count its launches
     T = shape["steps_per_launch"]
     member_launches, left = 0, steps
     while left > 0:
         lim = min(left, shape["graph_steps"])
-        kk = T if (T > 1 and lim >= T) else 1
-        while kk * 2 <= lim:
-            kk *= 2
-        q = kk // T if (T > 1 and kk >= T) else 0
-        member_launches += q + (kk - q * T)
+        if T > 1 and lim >= T:
+            kk = T
+            while kk * 2 <= lim:
+                kk *= 2
+            member_launches += kk // T
+        elif T > 1:
+            kk = lim                    # one pass of the remaining steps (one step: one launch)
+            member_launches += 1
+        else:
+            kk = 1
+            while kk * 2 <= lim:
+                kk *= 2
+            member_launches += kk
         left -= kk
     alg = 72 * cells * member_launches
     return {

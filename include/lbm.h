@@ -269,9 +269,10 @@ LBM_API int32_t lbm_steps_per_launch(const lbm_launch *cfg);
  * one launch advances every member by T steps (strip tasks of the
  * several-steps-per-pass kernel, see lbm_launch variants 8-13) and a member
  * whose remaining count is not a multiple of T takes its last steps in
- * one-step launches; step loops of T 2^m steps (or powers of two below T)
- * up to graph_steps, each with as many one-step launches as its members
- * need, are recorded once as HIP graphs and replayed
+ * one-step launches; step loops of T 2^m steps up to graph_steps (at the
+ * end of a run, the r < T remaining steps as one pass of r steps), each with
+ * as many one-step launches as its members need, are recorded once as HIP
+ * graphs and replayed
  * (lbm_pool_step(n) runs n steps as a few such replays).  Each
  * member carries its own step count: a member added with nsteps stops after
  * exactly nsteps steps, independently of the others, and is then returned by
@@ -294,8 +295,8 @@ typedef struct lbm_pool lbm_pool;
  *   block        threads per workgroup of the one-step launch, multiple of
  *                64, 64 .. 1024
  *   grid         workgroups of a persistent launch (both kinds), 1 .. 2^20
- *   graph_steps  longest recorded step loop (a loop is T 2^m steps, or a
- *                power of two below T), 1 .. 1024
+ *   graph_steps  longest recorded step loop (a loop is T 2^m steps, or
+ *                fewer than T), 1 .. 1024
  *   steps_per_launch  T = 1, 2, 4, 5, 6 or 7; T > 1 adds strip tasks (columns
  *                as for lbm_launch variants 8-13) of seg_rows rows, one wave
  *                each

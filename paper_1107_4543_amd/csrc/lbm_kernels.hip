@@ -1429,6 +1429,7 @@ void *pool_multi_typed(int T, int flags)
     if (T == T_ && flags == F_) return reinterpret_cast<void *>(&k_pool_multi<S, C, T_, F_>);
 #define LBM_PM_T(T_) LBM_PM(T_, 0) LBM_PM(T_, 2) LBM_PM(T_, 4) LBM_PM(T_, 12)
     LBM_PM_T(2)
+    LBM_PM_T(3)
     LBM_PM_T(4)
     LBM_PM_T(5)
     LBM_PM_T(6)

@@ -79,7 +79,7 @@ struct lbm_pool {
     lbm_pool_shape shape{256, 512, 4096, 256, 7, 32, 4, 12};
     std::vector<Slot> slots;
     std::vector<int> finishing;      // slot indices in completion order
-    std::map<std::tuple<unsigned, int, int, int, int>, GraphEntry> graphs;   // (class mask, steps, one-step launches, grids)
+    std::map<std::tuple<unsigned, int, int, int, int, int>, GraphEntry> graphs;   // (class mask, steps, steps per T-step launch, one-step launches, grids)
 };
 
 namespace {
@@ -262,12 +262,11 @@ int multi_grid(const lbm_pool *P)
 // launches, one node per class in `mask`, each depending on the previous
 // launch), then the commit kernel.  The one-step launches a member takes in
 // the chunk come first, so nsingle only has to cover the largest such count
-// among the members.
-lbm_status get_graph(lbm_pool *P, unsigned mask, int len, int nsingle, hipGraphExec_t *out)
+// among the members.  T is the chunk's steps per T-step launch (chunk_steps).
+lbm_status get_graph(lbm_pool *P, unsigned mask, int len, int T, int nsingle, hipGraphExec_t *out)
 {
     const int grid = launch_grid(P), mgrid = multi_grid(P);
-    const int T = P->shape.steps_per_launch;
-    auto key = std::make_tuple(mask, len, nsingle, grid, mgrid);
+    auto key = std::make_tuple(mask, len, T, nsingle, grid, mgrid);
     auto it = P->graphs.find(key);
     if (it != P->graphs.end()) {
         *out = it->second.exec;
@@ -331,6 +330,19 @@ lbm_status get_graph(lbm_pool *P, unsigned mask, int len, int nsingle, hipGraphE
     return LBM_OK;
 }
 
+// Steps per T-step launch in a chunk of kk steps: the shape's T, or for a
+// chunk shorter than T (the end of a run) kk itself, so that the chunk is
+// one pass of kk steps over the same strip tasks (their width fits any
+// smaller T) when that kernel exists for every class present.
+int chunk_steps(const lbm_pool *P, int kk)
+{
+    const int T = P->shape.steps_per_launch;
+    if (T < 2 || kk >= T || kk < 2) return T;
+    for (int c = 0; c < lbm::kClasses; ++c)
+        if ((P->class_mask & (1u << c)) && !lbm::pool_multi_kernel(c, kk, P->shape.flags)) return T;
+    return kk;
+}
+
 // Advances every active member by min(kk, remaining) with one recorded loop
 // of kk steps (kk <= graph_steps), holding as many one-step launches as the
 // members need in it.
@@ -338,7 +350,7 @@ lbm_status run_chunk(lbm_pool *P, int kk)
 {
     hipError_t e;
     hipGraphExec_t ex;
-    const int T = P->shape.steps_per_launch;
+    const int T = chunk_steps(P, kk);
     int64_t need = 0;
     for (const Slot &s : P->slots) {
         if (!s.lat || s.finishing) continue;
@@ -346,7 +358,7 @@ lbm_status run_chunk(lbm_pool *P, int kk)
         need = std::max(need, std::min<int64_t>(rem, kk) - lbm::member_multi(rem, kk, T) * T);
     }
     need = std::min<int64_t>(need, lbm::chunk_single_launches(kk, T));
-    lbm_status st = get_graph(P, P->class_mask, kk, (int)need, &ex);
+    lbm_status st = get_graph(P, P->class_mask, kk, T, (int)need, &ex);
     if (st != LBM_OK) return st;
     if ((e = hipGraphLaunch(ex, P->stream)) != hipSuccess) return phip(e, "hipGraphLaunch");
     for (int i = 0; i < P->max_members; ++i) {
@@ -354,9 +366,9 @@ lbm_status run_chunk(lbm_pool *P, int kk)
         if (!s.lat || s.finishing) continue;
         const int64_t rem = s.t_target - s.t_done;
         const int64_t span = std::min<int64_t>(rem, kk);
-        const int64_t q = lbm::member_multi(rem, kk, P->shape.steps_per_launch);
+        const int64_t q = lbm::member_multi(rem, kk, T);
         s.t_done += span;
-        s.flips += q + span - q * P->shape.steps_per_launch;
+        s.flips += q + span - q * T;
         if (s.t_done >= s.t_target) {
             s.finishing = true;
             if ((e = hipEventRecord(s.ev_done, P->stream)) != hipSuccess) return phip(e, "hipEventRecord");
@@ -529,13 +541,17 @@ lbm_status lbm_pool_step(lbm_pool *pool, int64_t nsteps)
         lbm_status st = upload(pool);
         if (st != LBM_OK) return st;
         // the longest recorded loop that fits: T 2^m steps (only T-step
-        // launches for members that stay), or a power of two below T
+        // launches for members that stay); below T, the rest in one chunk
+        // (one shorter pass, see chunk_steps); one step per launch: powers
+        // of two
         const int64_t lim = std::min<int64_t>({nsteps, (int64_t)pool->shape.graph_steps, max_rem});
         const int T = pool->shape.steps_per_launch;
         int kk = 1;
         if (T > 1 && lim >= T) {
             kk = T;
             while ((int64_t)kk * 2 <= lim) kk *= 2;
+        } else if (T > 1) {
+            kk = (int)lim;
         } else {
             while ((int64_t)kk * 2 <= lim) kk *= 2;
         }
