@@ -161,13 +161,36 @@ def copy_probe(nbytes, reps):
             "GBps": round(2 * nbytes / (us * 1e-6) / 1e9, 1)}
 
 
-def pool_roofline(T, cells, launches, ms):
+def read_pool_traffic(shape):
+    """Measured HBM bytes per T-step launch of the pool kernel on batch256
+    from the committed counter summary, or None when absent, taken on a
+    different kernel source or with a different T-step shape."""
+    path = os.path.join(ROOT, "profiles", "traffic_pool_multi_f32_batch256.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    want = ",".join(str(shape[k]) for k in ("steps_per_launch", "seg_rows", "waves", "flags"))
+    if kv.get("pool_multi_shape") != want:
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def pool_roofline(T, cells, launches, ms, traffic=None):
     """Roofline of the pool's step kernel over a timed pass: HBM for one step
     per launch, the vector ALU (algorithmic operations, FP32) for T > 1."""
     us = 1e3 * ms / launches
     gbps = 72 * cells / (us * 1e-6) / 1e9
     hbm = {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-           "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": None, "algorithmic_bytes_per_launch": 72 * cells}
+           "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": traffic, "algorithmic_bytes_per_launch": 72 * cells}
     common = {"kernel": ("k_pool_multi (%d steps per launch, persistent, per storage class)" % T if T > 1
                          else "k_pool_step (persistent, per storage class)"),
               "steps_per_launch": T, "launches": launches, "avg_launch_us": round(us, 3)}
@@ -177,7 +200,7 @@ def pool_roofline(T, cells, launches, ms):
     tops = ops / (us * 1e-6) / 1e12
     peak = ALU_PEAK["f32"] / 1e12
     return dict({"bound": "alu", "achieved": round(tops, 2), "peak": round(peak, 2), "unit": "T F32 ops/s",
-                 "frac": round(tops / peak, 4), "traffic": None, "algorithmic_ops_per_launch": ops,
+                 "frac": round(tops / peak, 4), "traffic": traffic, "algorithmic_ops_per_launch": ops,
                  "ops_per_update": ALG_OPS_PER_LU, "hbm": hbm}, **common)
 
 
@@ -241,15 +264,17 @@ def bench_batch256(args):
         pool.poll(wait=True)
     batched_rho = [lat.moments()[0] for lat in lats]
 
-    init_all()
-    torch.cuda.synchronize()
-    e0.record()
-    for lat in lats:
-        lat.step(steps)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_seq = e0.elapsed_time(e1)
-    equal = all(torch.equal(r, lat.moments()[0]) for r, lat in zip(batched_rho, lats))
+    ms_seq, equal = None, None
+    if not args.no_sequential:
+        init_all()
+        torch.cuda.synchronize()
+        e0.record()
+        for lat in lats:
+            lat.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_seq = e0.elapsed_time(e1)
+        equal = all(torch.equal(r, lat.moments()[0]) for r, lat in zip(batched_rho, lats))
     pool.close()
 
     lups = cells * steps
@@ -282,12 +307,13 @@ def bench_batch256(args):
         "config": {"workload": "batch256", "lattices": len(specs), "cells": cells, "steps": steps,
                    "seed": w["seed"], "pool_shape": shape, "stability_draws": draws[0],
                    "stability_acceptance": round(len(specs) / draws[0], 4)},
-        "roofline": pool_roofline(T, cells, member_launches, ms_batched),
-        "sequential_plain": {"value": round(lups / (ms_seq / 1e3) / 1e6, 1), "unit": "MLUPS",
-                             "ms": round(ms_seq, 2), "launches": len(specs) * steps,
-                             "launch_shape": lats[0].launch},
-        "speedup_vs_sequential": round(ms_seq / ms_batched, 3),
-        "bitwise_equal_to_sequential": bool(equal),
+        "roofline": pool_roofline(T, cells, member_launches, ms_batched, read_pool_traffic(shape)),
+        "sequential_plain": None if ms_seq is None else {
+            "value": round(lups / (ms_seq / 1e3) / 1e6, 1), "unit": "MLUPS", "ms": round(ms_seq, 2),
+            "launches": len(specs) * steps, "launch_shape": lats[0].launch},
+        "speedup_vs_sequential": None if ms_seq is None else round(ms_seq / ms_batched, 3),
+        "bitwise_equal_to_sequential": None if equal is None else bool(equal),
+        "context": {"copy_probe": copy_probe(603979776, 10)},
     }
 
 
@@ -417,6 +443,8 @@ def main():
     ap.add_argument("--launch", default=None,
                     help="launch shape variant,block_x,block_y,rows,xcd_remap,flags (default: the recorded "
                          "tuned shape for the storage type)")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batch256: skip the one-lattice-at-a-time comparison (for counter profiling)")
     ap.add_argument("--pool-shape", default=None,
                     help="batch256: pool shape tile_cells,block,grid,graph_steps,steps_per_launch,seg_rows,waves,"
                          "flags (no tuning)")
