@@ -455,7 +455,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the lattice path is single-GPU in this build "
+        print("bench.py measures one GPU only: the lattice path runs on one GPU "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 

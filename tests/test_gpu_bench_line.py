@@ -1,5 +1,5 @@
-"""The JSON line bench.py prints for the 4096^2 wave workload: the fields the
-round-end measurement reads, and a roofline whose bound matches the launch
+"""The JSON line bench.py prints for the 4096^2 wave workload: the fields a
+measurement harness reads, and a roofline whose bound matches the launch
 shape (vector ALU for several steps per launch, HBM for one step)."""
 import json
 import os
