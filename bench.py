@@ -120,25 +120,53 @@ def build_waves4096(storage):
     return lat, cfg, rates, (rho, ux, uy), w
 
 
-def cpu_baseline(rates, fields1, nx, ny, u0x, budget_s):
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(rates, fields1, nx, ny, u0x, budget_s, budget_1t_s):
     """FP64 oracle (as it stands) on the full lattice for as many whole steps
-    as fit in about budget_s seconds (at least one)."""
+    as fit in about budget_s seconds (at least one) with its default OpenMP
+    threads, and for about budget_1t_s seconds on one thread."""
     import numpy as np
 
     import oracle
     rho, ux, uy = (np.ascontiguousarray(np.broadcast_to(a, (ny, nx))) for a in fields1)
     f = oracle.init(rho, ux, uy)
     del rho, ux, uy
-    steps, elapsed = 0, 0.0
-    while elapsed < budget_s:
-        t0 = time.perf_counter()
-        f = oracle.run(f, rates, 1)
-        elapsed += time.perf_counter() - t0
-        steps += 1
-    return {"value": nx * ny * steps / elapsed / 1e6, "unit": "MLUPS", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"FP64 oracle (unfused collide then stream) on the full {nx}x{ny} lattice, "
-                      f"{steps} step(s), {elapsed:.1f} s"}
+
+    def timed(budget):
+        nonlocal f
+        steps, elapsed = 0, 0.0
+        while elapsed < budget or steps == 0:
+            t0 = time.perf_counter()
+            f = oracle.run(f, rates, 1)
+            elapsed += time.perf_counter() - t0
+            steps += 1
+        return steps, elapsed
+
+    cores = oracle.threads()
+    steps, elapsed = timed(budget_s)
+    out = {"value": nx * ny * steps / elapsed / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+           "sample": f"FP64 oracle (unfused collide then stream) on the full {nx}x{ny} lattice, "
+                     f"{steps} step(s), {elapsed:.1f} s, {cores} OpenMP threads",
+           "cpu_model": cpu_model(), "host_logical_cpus": os.cpu_count()}
+    if budget_1t_s > 0:
+        oracle.set_threads(1)
+        try:
+            steps1, elapsed1 = timed(budget_1t_s)
+        finally:
+            oracle.set_threads(cores)
+        out["one_thread"] = {"value": nx * ny * steps1 / elapsed1 / 1e6, "unit": "MLUPS", "cores": 1,
+                             "sample": f"same, {steps1} step(s), {elapsed1:.1f} s, 1 thread"}
+    return out
 
 
 def copy_probe(nbytes, reps):
@@ -184,9 +212,11 @@ def read_pool_traffic(shape):
         return None
 
 
-def pool_roofline(T, cells, launches, ms, traffic=None):
-    """Roofline of the pool's step kernel over a timed pass: HBM for one step
-    per launch, the vector ALU (algorithmic operations, FP32) for T > 1."""
+def pool_roofline(T, cells, launches, ms, traffic=None, steps=None):
+    """Roofline of the pool's step kernel over a timed pass of `steps` steps
+    that each member takes in `launches` launches: HBM for one step per
+    launch, the vector ALU (algorithmic operations, FP32) for T > 1, counting
+    the updates of the steps actually run."""
     us = 1e3 * ms / launches
     gbps = 72 * cells / (us * 1e-6) / 1e9
     hbm = {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -196,28 +226,67 @@ def pool_roofline(T, cells, launches, ms, traffic=None):
               "steps_per_launch": T, "launches": launches, "avg_launch_us": round(us, 3)}
     if T == 1:
         return dict(hbm, **common)
-    ops = ALG_OPS_PER_LU * cells * T
-    tops = ops / (us * 1e-6) / 1e12
+    steps = launches * T if steps is None else steps
+    ops = ALG_OPS_PER_LU * cells * steps
+    tops = ops / (ms * 1e-3) / 1e12
     peak = ALU_PEAK["f32"] / 1e12
     return dict({"bound": "alu", "achieved": round(tops, 2), "peak": round(peak, 2), "unit": "T F32 ops/s",
-                 "frac": round(tops / peak, 4), "traffic": traffic, "algorithmic_ops_per_launch": ops,
+                 "frac": round(tops / peak, 4), "traffic": traffic,
+                 "algorithmic_ops_per_launch": round(ops / launches), "algorithmic_ops_timed": ops,
                  "ops_per_update": ALG_OPS_PER_LU, "hbm": hbm}, **common)
 
 
-def bench_batch256(args):
+# Pool shape the pool tuner selected for batch256 on MI355X (seven steps per
+# launch, 32-row strip tasks, 4 waves per workgroup, flags 12).
+DEFAULT_POOL_SHAPE = "256,512,4096,256,7,32,4,12"
+POOL_SHAPE_KEYS = ["tile_cells", "block", "grid", "graph_steps", "steps_per_launch", "seg_rows", "waves", "flags"]
+
+
+def parse_pool_shape(text):
+    vals = [int(v) for v in text.split(",")]
+    if len(vals) != len(POOL_SHAPE_KEYS):
+        raise SystemExit("--pool-shape takes " + ",".join(POOL_SHAPE_KEYS))
+    return dict(zip(POOL_SHAPE_KEYS, vals))
+
+
+def pool_member_launches(shape, steps):
+    """Launches each member takes for `steps` steps: replays the pool's
+    chunking (loops of T 2^m steps, then the remaining r < T steps as one
+    pass)."""
+    T = shape["steps_per_launch"]
+    member_launches, left = 0, steps
+    while left > 0:
+        lim = min(left, shape["graph_steps"])
+        if T > 1 and lim >= T:
+            kk = T
+            while kk * 2 <= lim:
+                kk *= 2
+            member_launches += kk // T
+        elif T > 1:
+            kk = lim                    # one pass of the remaining steps (one step: one launch)
+            member_launches += 1
+        else:
+            kk = 1
+            while kk * 2 <= lim:
+                kk *= 2
+            member_launches += kk
+        left -= kk
+    return member_launches
+
+
+def run_batch256(steps, pool_shape=None, sequential=True):
     """256 independent lattices (sides log-uniform in [64, 1024], sampled
-    stable rates, one pulse each, FP32, 500 steps): the whole job in one pool
-    (persistent launches of several steps each, recorded step loop, tuned
-    shape) against the same
-    256 lattices run one after another with one plain launch per step.  The
-    two give bit-identical fields (checked)."""
+    stable rates, one pulse each, FP32): `steps` steps of all of them in one
+    pool (persistent launches of several steps each, recorded step loop;
+    pool_shape fixed, or tuned when None), timed with HIP events on the
+    pool's stream, against the same 256 lattices run one after another with
+    each lattice's default launches.  Returns a dict of the measurements."""
     import torch
 
     import lbm_inputs
     from paper_1107_4543_amd import Lattice, stability
     from paper_1107_4543_amd.pool import Pool
     w = lbm_inputs.WORKLOADS["batch256"]
-    steps = w["steps"] if args.steps == 2000 else args.steps
     draws = [0]
 
     def accept(relax):
@@ -238,12 +307,8 @@ def bench_batch256(args):
     init_all()
     for lat in lats:
         pool.add(lat, steps)
-    if args.pool_shape:
-        keys = ["tile_cells", "block", "grid", "graph_steps", "steps_per_launch", "seg_rows", "waves", "flags"]
-        vals = [int(v) for v in args.pool_shape.split(",")]
-        if len(vals) != len(keys):
-            raise SystemExit("--pool-shape takes " + ",".join(keys))
-        pool.set_shape(**dict(zip(keys, vals)))
+    if pool_shape:
+        pool.set_shape(**pool_shape)
         shape = pool.shape
     else:
         shape, _ = pool.tune(reps=3)
@@ -265,7 +330,7 @@ def bench_batch256(args):
     batched_rho = [lat.moments()[0] for lat in lats]
 
     ms_seq, equal = None, None
-    if not args.no_sequential:
+    if sequential:
         init_all()
         torch.cuda.synchronize()
         e0.record()
@@ -276,43 +341,51 @@ def bench_batch256(args):
         ms_seq = e0.elapsed_time(e1)
         equal = all(torch.equal(r, lat.moments()[0]) for r, lat in zip(batched_rho, lats))
     pool.close()
+    return {"ms_batched": ms_batched, "ms_seq": ms_seq, "equal": equal, "shape": shape, "cells": cells,
+            "lattices": len(specs), "draws": draws[0], "seq_launch": lats[0].launch, "seed": w["seed"]}
 
-    lups = cells * steps
-    # each member reads and writes its nine planes once per launch it takes;
-    # replay the pool's chunking (loops of T 2^m steps, then the remaining
-    # r < T steps as one pass) to count its launches
-    T = shape["steps_per_launch"]
-    member_launches, left = 0, steps
-    while left > 0:
-        lim = min(left, shape["graph_steps"])
-        if T > 1 and lim >= T:
-            kk = T
-            while kk * 2 <= lim:
-                kk *= 2
-            member_launches += kk // T
-        elif T > 1:
-            kk = lim                    # one pass of the remaining steps (one step: one launch)
-            member_launches += 1
-        else:
-            kk = 1
-            while kk * 2 <= lim:
-                kk *= 2
-            member_launches += kk
-        left -= kk
-    alg = 72 * cells * member_launches
+
+def batch_summary(r, steps):
+    """MLUPS, roofline and comparison figures of a run_batch256 result."""
+    lups = r["cells"] * steps
+    T = r["shape"]["steps_per_launch"]
+    member_launches = pool_member_launches(r["shape"], steps)
+    ms_seq = r["ms_seq"]
     return {
-        "metric": METRIC, "value": round(lups / (ms_batched / 1e3) / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
-        "steps": steps, "warmup": steps, "ms_per_step": round(ms_batched / steps, 5), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "batch256", "lattices": len(specs), "cells": cells, "steps": steps,
-                   "seed": w["seed"], "pool_shape": shape, "stability_draws": draws[0],
-                   "stability_acceptance": round(len(specs) / draws[0], 4)},
-        "roofline": pool_roofline(T, cells, member_launches, ms_batched, read_pool_traffic(shape)),
+        "value": round(lups / (r["ms_batched"] / 1e3) / 1e6, 1), "unit": "MLUPS", "steps": steps,
+        "ms_per_step": round(r["ms_batched"] / steps, 5),
+        "roofline": pool_roofline(T, r["cells"], member_launches, r["ms_batched"], read_pool_traffic(r["shape"]),
+                                  steps=steps),
         "sequential_plain": None if ms_seq is None else {
             "value": round(lups / (ms_seq / 1e3) / 1e6, 1), "unit": "MLUPS", "ms": round(ms_seq, 2),
-            "launches": len(specs) * steps, "launch_shape": lats[0].launch},
-        "speedup_vs_sequential": None if ms_seq is None else round(ms_seq / ms_batched, 3),
-        "bitwise_equal_to_sequential": None if equal is None else bool(equal),
+            "launch_shape_of_first_lattice": r["seq_launch"]},
+        "speedup_vs_sequential": None if ms_seq is None else round(ms_seq / r["ms_batched"], 3),
+        "bitwise_equal_to_sequential": None if r["equal"] is None else bool(r["equal"]),
+    }
+
+
+def bench_batch256(args):
+    """256 independent lattices (sides log-uniform in [64, 1024], sampled
+    stable rates, one pulse each, FP32, 500 steps): the whole job in one pool
+    against the same 256 lattices run one after another with each lattice's
+    default launches.  The two give bit-identical fields (checked)."""
+    import lbm_inputs
+    w = lbm_inputs.WORKLOADS["batch256"]
+    steps = w["steps"] if args.steps == 2000 else args.steps
+    shape = parse_pool_shape(args.pool_shape) if args.pool_shape else None
+    r = run_batch256(steps, shape, sequential=not args.no_sequential)
+    summ = batch_summary(r, steps)
+    return {
+        "metric": METRIC, "value": summ["value"], "unit": "MLUPS", "n_gpus": 1,
+        "steps": steps, "warmup": steps, "ms_per_step": summ["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch256", "lattices": r["lattices"], "cells": r["cells"], "steps": steps,
+                   "seed": r["seed"], "pool_shape": r["shape"], "stability_draws": r["draws"],
+                   "stability_acceptance": round(r["lattices"] / r["draws"], 4)},
+        "roofline": summ["roofline"],
+        "sequential_plain": summ["sequential_plain"],
+        "speedup_vs_sequential": summ["speedup_vs_sequential"],
+        "bitwise_equal_to_sequential": summ["bitwise_equal_to_sequential"],
         "context": {"copy_probe": copy_probe(603979776, 10)},
     }
 
@@ -321,8 +394,12 @@ def bench_serve(args):
     """Poisson arrivals of simulation jobs (square side log-uniform in
     [128, 4096], steps uniform in [200, 5000], FP32 or FP16 storage 50/50,
     sampled stable rates, pulse or plane-wave initial fields), served with
-    continuous batching under an HBM budget and, on the same trace, one job
-    at a time with plain launches.  Latency = arrival to result on the host."""
+    continuous batching under an HBM budget (admission: shortest job first
+    with ageing, the server's default; also plain shortest job first and
+    arrival order) and, on the same trace, one job at a time with each
+    lattice's default launches.  Latency = arrival to result on the host.
+    Every job's final raw state is compared between the modes through an
+    on-device digest of its stored values."""
     import lbm_inputs
     from paper_1107_4543_amd import stability
     from paper_1107_4543_amd.serve import Server, run_plain, summarize
@@ -330,19 +407,22 @@ def bench_serve(args):
     budget = int(args.budget_gb * 1e9)
     for i, rate in enumerate(float(r) for r in args.rates.split(",")):
         trace = lbm_inputs.serving_trace(100 + i, rate, args.jobs, accept=stability.stable)
-        srv = Server(budget, max_members=256, policy="sjf")
-        served = srv.run(trace)
-        srv.close()
-        fifo = Server(budget, max_members=256, policy="fifo")
-        served_fifo = fifo.run(trace)
-        fifo.close()
-        plain = run_plain(trace)
-        pd = {r.tag: r.diag for r in plain}
-        equal = all(r.diag == pd[r.tag] for r in served + served_fifo)
-        row = {"rate_jobs_per_s": rate, "jobs": len(trace), "served": summarize(served),
-               "served_fifo": summarize(served_fifo), "plain": summarize(plain),
-               "equal_results": bool(equal), "rejected": len(srv.rejected),
-               "peak_members": srv.peak_members, "peak_budget_gb": round(srv.peak_used / 1e9, 2)}
+        modes = {}
+        peak = {}
+        for policy in ("aged", "sjf", "fifo"):
+            srv = Server(budget, max_members=256, policy=policy, keep="digest")
+            modes[policy] = srv.run(trace)
+            srv.close()
+            peak[policy] = (srv.peak_members, round(srv.peak_used / 1e9, 2), len(srv.rejected))
+        plain = run_plain(trace, keep="digest")
+        pd = {r.tag: r.digest for r in plain}
+        mismatched = sorted({r.tag for rs in modes.values() for r in rs if r.digest != pd.get(r.tag)})
+        row = {"rate_jobs_per_s": rate, "jobs": len(trace), "served": summarize(modes["aged"]),
+               "served_sjf": summarize(modes["sjf"]), "served_fifo": summarize(modes["fifo"]),
+               "plain": summarize(plain),
+               "equal_results": not mismatched and all(len(rs) == len(trace) for rs in modes.values()),
+               "jobs_compared": sum(len(rs) for rs in modes.values()), "mismatched_jobs": mismatched,
+               "rejected": peak["aged"][2], "peak_members": peak["aged"][0], "peak_budget_gb": peak["aged"][1]}
         out.append(row)
         print(json.dumps({"progress": row}), file=sys.stderr, flush=True)
     top = out[-1]["served"]
@@ -350,7 +430,7 @@ def bench_serve(args):
             "steps": None, "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f32/f16", "data": "synthetic",
             "config": {"workload": "serve", "jobs_per_rate": args.jobs, "budget_gb": args.budget_gb,
-                       "rates": args.rates},
+                       "rates": args.rates, "admission": "aged shortest-job-first (also sjf, fifo)"},
             "serving": out}
 
 
@@ -436,7 +516,7 @@ def main():
                     help="waves4096: one 4096^2 lattice (default); batch256: 256 lattices, pool vs "
                          "sequential; serve: Poisson job traces, continuous batching vs plain FIFO")
     ap.add_argument("--rates", default="10,30,100,300,1000", help="serve: arrival rates (jobs/s)")
-    ap.add_argument("--jobs", type=int, default=40, help="serve: jobs per rate")
+    ap.add_argument("--jobs", type=int, default=200, help="serve: jobs per rate")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget for admitted jobs")
     ap.add_argument("--no-tune", action="store_true", help="use the library's default launch shape (four steps per launch from 2^22 cells)")
     ap.add_argument("--tune", action="store_true", help="search the launch shape with lbm_tune before timing")
@@ -452,6 +532,10 @@ def main():
                     help="run only the device-to-device copy probe")
     ap.add_argument("--probe-bytes", type=int, default=1 << 30)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work (0 = skip)")
+    ap.add_argument("--cpu-budget-1t", type=float, default=5.0,
+                    help="seconds of one-thread oracle work (0 = skip)")
+    ap.add_argument("--batched-steps", type=int, default=500,
+                    help="default workload: steps of the batched 256-lattice run reported beside it (0 = skip)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -485,27 +569,30 @@ def main():
 
     stream = lat.stream
     lat.step(args.warmup)
+    spl = lat.steps_per_launch
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    lat.step(args.steps)
-    e1.record(stream)
+    # The timed region is args.steps steps on the lattice's stream.  With a
+    # several-steps shape it is issued one launch of spl steps at a time, a
+    # HIP event after each, so the dominant kernel's own launches are timed
+    # apart from the one shorter launch that takes the steps left over.
+    full, rest = (args.steps // spl, args.steps % spl) if spl > 1 else (0, args.steps)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(full + 2)]
+    ev[0].record(stream)
+    for i in range(full):
+        lat.step(spl)
+        ev[i + 1].record(stream)
+    if rest:
+        lat.step(rest)
+    ev[full + 1].record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    ms = ev[0].elapsed_time(ev[full + 1])
     st, diag = lat.diagnostics()
     assert st == 0, "non-finite state after the timed steps"
 
     cells = lat.nx * lat.ny
     mlups = cells * args.steps / (ms / 1e3) / 1e6
-    # a launch advances steps_per_launch steps (several steps per pass keep
-    # the intermediate rows in registers) and reads and writes every
-    # population once: 2 * 9 * sizeof(storage) bytes per cell and launch
-    spl = lat.steps_per_launch
     launches = lat.launches_for(args.steps)             # T-step launches and the left-over one(s)
-    us_per_launch = 1e3 * ms / launches
     alg_bytes = 2 * 9 * STORE_BYTES[args.storage] * cells
-    achieved = alg_bytes / (us_per_launch * 1e-6) / 1e9
     traffic = read_traffic("waves4096", args.storage, lat.launch)
 
     out = {
@@ -514,39 +601,77 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.storage, "data": "synthetic", "config": cfg,
     }
-    hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-           "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-           "algorithmic_bytes_per_launch": alg_bytes}
-    common = {"kernel": ("k_step_multi (%d steps per pass)" % spl if spl > 1
-                         else "k_step (fused collide + pull stream)"),
-              "steps_per_launch": spl, "launches": launches, "avg_launch_us": round(us_per_launch, 3)}
+    # one pass per step would move 2 * 9 * sizeof(storage) bytes per update:
+    # the bytes a one-pass kernel needs for this many updates per second
+    one_pass = alg_bytes * args.steps / (ms * 1e-3) / 1e9
+    one_pass_equiv = {"achieved": round(one_pass, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                      "frac": round(one_pass / HBM_PEAK_GBPS, 4),
+                      "bytes_per_update": 2 * 9 * STORE_BYTES[args.storage]}
     if spl == 1:
         # one step per launch: every update reads and writes all nine planes
-        out["roofline"] = dict(hbm, **common)
+        us = 1e3 * ms / launches
+        achieved = alg_bytes / (us * 1e-6) / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                           "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                           "algorithmic_bytes_per_launch": alg_bytes,
+                           "kernel": "k_step (fused collide + pull stream)", "steps_per_launch": 1,
+                           "launches": launches, "avg_launch_us": round(us, 3)}
     else:
         # several steps per launch move a T-th of the bytes per update; the
-        # bound is the vector ALU: algorithmic operations per launch over the
-        # launch time, against the non-packed issue peak of the compute type
+        # bound is the vector ALU: the collision's algorithmic operations of
+        # the spl steps one launch of the dominant kernel advances, over that
+        # kernel's average launch duration (its own launches' events),
+        # against the non-packed issue peak of the compute type
         compute = lat.compute
-        ops = ALG_OPS_PER_LU * cells * spl
-        tops = ops / (us_per_launch * 1e-6) / 1e12
         peak = ALU_PEAK[compute] / 1e12
-        out["roofline"] = dict({"bound": "alu", "achieved": round(tops, 2), "peak": round(peak, 2),
-                                "unit": "T %s ops/s" % compute.upper(), "frac": round(tops / peak, 4),
-                                "traffic": traffic, "algorithmic_ops_per_launch": ops,
-                                "ops_per_update": ALG_OPS_PER_LU, "hbm": hbm}, **common)
+        # (fewer steps than one launch: the region's single shorter launch)
+        us = 1e3 * ev[0].elapsed_time(ev[full]) / full if full else 1e3 * ms / launches
+        ops = ALG_OPS_PER_LU * cells * spl
+        tops = ops / (us * 1e-6) / 1e12
+        # the same over the whole timed region, from the steps actually run
+        tops_all = ALG_OPS_PER_LU * cells * args.steps / (ms * 1e-3) / 1e12
+        achieved_b = alg_bytes / (us * 1e-6) / 1e9
+        hbm = {"bound": "hbm", "achieved": round(achieved_b, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+               "frac": round(achieved_b / HBM_PEAK_GBPS, 4), "traffic": traffic,
+               "algorithmic_bytes_per_launch": alg_bytes,
+               "reading": "bytes one launch of the dominant kernel moves (it reads and writes every "
+                          "population once for spl steps) over its average launch duration"}
+        out["roofline"] = {"bound": "alu", "achieved": round(tops, 2), "peak": round(peak, 2),
+                           "unit": "T %s ops/s" % compute.upper(), "frac": round(tops / peak, 4),
+                           "traffic": traffic, "algorithmic_ops_per_launch": ops,
+                           "ops_per_update": ALG_OPS_PER_LU,
+                           "kernel": "k_step_multi (%d steps per pass)" % spl, "steps_per_launch": spl,
+                           "launches_timed": full, "avg_launch_us": round(us, 3),
+                           "timed_region": {"steps": args.steps, "launches": launches, "ms": round(ms, 4),
+                                            "achieved": round(tops_all, 2), "frac": round(tops_all / peak, 4),
+                                            "leftover_launch_steps": rest},
+                           "hbm": hbm, "one_pass_equiv": one_pass_equiv}
         kv = read_profile("waves4096", args.storage, lat.launch)
         if kv and "valu_lane_instructions_per_update" in kv:
             # what the compiled loop issues per useful update (halo lanes,
             # prologue rows and register moves included), see the profile
             per_lu = float(kv["valu_lane_instructions_per_update"])
+            rate = cells * spl / (us * 1e-6)
             out["roofline"]["valu_issue"] = {"lane_instructions_per_update": per_lu,
-                                             "achieved": round(per_lu * mlups * 1e6 / 1e12, 2),
+                                             "achieved": round(per_lu * rate / 1e12, 2),
                                              "peak": round(VALU_PEAK / 1e12, 2), "unit": "T lane-instr/s",
-                                             "frac": round(per_lu * mlups * 1e6 / VALU_PEAK, 4)}
+                                             "frac": round(per_lu * rate / VALU_PEAK, 4)}
+    if spl == 1:
+        out["roofline"]["one_pass_equiv"] = one_pass_equiv
     out["context"] = {"copy_probe": copy_probe(alg_bytes // 2, 10), "device": torch.cuda.get_device_name(0)}
+    del lat
+    if args.batched_steps > 0:
+        # the batched workload (256 lattices) with the recorded pool shape
+        import lbm_inputs
+        shape = parse_pool_shape(args.pool_shape or DEFAULT_POOL_SHAPE)
+        r = run_batch256(args.batched_steps, shape, sequential=True)
+        out["batched"] = dict({"workload": "batch256", "lattices": r["lattices"], "cells": r["cells"],
+                               "seed": r["seed"], "pool_shape": r["shape"],
+                               "job_steps": lbm_inputs.WORKLOADS["batch256"]["steps"]},
+                              **batch_summary(r, args.batched_steps))
     if args.cpu_budget > 0:
-        out["cpu_baseline"] = cpu_baseline(rates, fields1, lat.nx, lat.ny, w["u0x"], args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(rates, fields1, cfg["nx"], cfg["ny"], w["u0x"], args.cpu_budget,
+                                           args.cpu_budget_1t)
     print(json.dumps(out), flush=True)
 
 

@@ -259,11 +259,12 @@ def batch_specs(seed: int, count: int = 256, side_range=(64, 1024), steps: int =
 
 def serving_trace(seed: int, rate: float, njobs: int, side_range=(128, 4096),
                   steps_range=(200, 5000),
-                  accept: Optional[Callable[[Dict[str, float]], bool]] = None) -> List[LatticeSpec]:
+                  accept: Optional[Callable[[Dict[str, float]], bool]] = None,
+                  storages=("f32", "f16")) -> List[LatticeSpec]:
     """A Poisson stream of simulation jobs (exponential inter-arrival times at
-    ``rate`` jobs/s): square side log-uniform, steps uniform, storage f32 or
-    f16 50/50, sampled relaxation set, pulse (A = 1e-3) or x-plane wave
-    (A = 1e-4, mode 1..8) 50/50."""
+    ``rate`` jobs/s): square side log-uniform, steps uniform, storage drawn
+    uniformly from ``storages`` (default f32 or f16 50/50), sampled relaxation
+    set, pulse (A = 1e-3) or x-plane wave (A = 1e-4, mode 1..8) 50/50."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
@@ -271,7 +272,7 @@ def serving_trace(seed: int, rate: float, njobs: int, side_range=(128, 4096),
         t += rng.exponential(1.0 / rate)
         side = _log_uniform_int(rng, *side_range)
         steps = int(rng.integers(steps_range[0], steps_range[1] + 1))
-        storage = "f32" if rng.uniform() < 0.5 else "f16"
+        storage = storages[min(int(rng.uniform() * len(storages)), len(storages) - 1)]
         while True:
             relax = draw_relaxation(rng)
             if accept is None or accept(relax):

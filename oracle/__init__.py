@@ -55,6 +55,8 @@ def _load():
     lib.oracle_moments.restype = None
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = None
     _lib = lib
     return lib
 
@@ -155,3 +157,8 @@ def moments(f):
 
 def threads():
     return int(_load().oracle_threads())
+
+
+def set_threads(n):
+    """Number of OpenMP threads for later calls (results do not depend on it)."""
+    _load().oracle_set_threads(int(n))

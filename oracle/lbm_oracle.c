@@ -243,3 +243,15 @@ int oracle_threads(void)
     return 1;
 #endif
 }
+
+/* Sets the number of OpenMP threads for the following calls (ignored
+ * without OpenMP); the arithmetic does not depend on it. */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -3,21 +3,29 @@
 A job is a lattice (size, relaxation rates, storage type, initial fields) and
 a number of steps.  ``Server.run`` replays a trace of jobs in real time:
 
-* jobs whose arrival time has passed wait in a FIFO queue;
+* jobs whose arrival time has passed wait in a queue, ordered by the
+  admission policy: shortest job first with ageing ("aged", the default:
+  least cells x steps first, but a job that has waited a fixed time plus
+  half its estimated service time goes ahead of all younger jobs, so no job
+  starves), plain shortest job first ("sjf") or arrival order ("fifo");
 * the head of the queue is admitted as soon as its device footprint fits in
-  the HBM budget and the pool has a free member slot: its workspace is
-  allocated, its fields are generated on the device and it joins the pool
-  (its state stays on the device for its whole life);
+  the HBM budget, the pool has a free member slot and the cells being
+  advanced stay under a cap: its workspace is allocated, its fields are
+  generated on the device and it joins the pool (its state stays on the
+  device for its whole life); a head that does not fit blocks the jobs
+  behind it (no backfilling), which bounds its wait;
 * the pool advances all admitted jobs together, one chunk of steps at a time
   (persistent batched launches, recorded step loop), with at most two chunks
   in flight so that admissions and completions are handled between chunks;
 * a job leaves the pool after exactly its own number of steps; its result
-  (FP64 mass/momentum diagnostics on the host, density/velocity fields on the
-  device) is read and its memory returned to the budget.
+  is read and its memory returned to the budget: the FP64 mass/momentum
+  diagnostics, and (``keep``) a digest of its raw final state, or the raw
+  state itself, or its FP64 density and velocity fields.
 
 ``run_plain`` serves the same trace one job at a time in arrival order with
-one plain launch per step, for comparison.  Both paths use the same per-cell
-arithmetic, so every job's result is bit-identical in the two.
+each lattice's own default launches, for comparison.  Both paths use the
+same per-cell arithmetic, so every job's final state is bit-identical in the
+two; the digests (or states) let a caller check that for every job.
 """
 import collections
 import math
@@ -48,6 +56,9 @@ class JobResult:
     storage: str
     diag: List[float] = field(default_factory=list)
     status: int = 0
+    digest: Optional[tuple] = None       # state_digest of the final raw state
+    state: Optional[object] = None       # final raw state bytes (host uint8 tensor)
+    fields: Optional[tuple] = None       # final (rho, ux, uy), host float64 arrays
 
     @property
     def latency(self):
@@ -78,6 +89,59 @@ def _new_lattice(spec, device, stream=None):
     return lat
 
 
+# odd 64-bit multipliers of the position-weighted digest
+_DIGEST_MUL, _DIGEST_ADD = 0x9E3779B97F4A7C15 - (1 << 64), 0x632BE59BD9B4E019
+
+
+_RAW_INT = {"f64": torch.int64, "f32": torch.int32, "f16": torch.int16, "bf16": torch.int16}
+
+
+def raw_state(lat):
+    """The lattice's raw stored populations as a [9, ny, nx] integer device
+    tensor (the storage type's bit patterns; the row padding that the
+    library's layout carries beyond nx is dropped), ordered on the
+    lattice's stream, and the step count t."""
+    buf, t = lat.save_state()
+    E = STORE_BYTES[lat.storage]
+    pitch = buf.numel() // (9 * lat.ny * E)
+    with torch.cuda.stream(lat.stream):
+        raw = buf.view(_RAW_INT[lat.storage]).view(9, lat.ny, pitch)[:, :, :lat.nx]
+    return raw, t
+
+
+def state_digest(lat):
+    """Digest of a lattice's raw state, computed on the device: the step
+    count and the wrapping int64 sums of the stored values' bit patterns and
+    of each pattern times an odd position-dependent multiplier.  Two states
+    with equal digests are equal except with negligible probability; any one
+    changed value changes both sums."""
+    raw, t = raw_state(lat)
+    with torch.cuda.stream(lat.stream):
+        words = raw.reshape(-1).to(torch.int64)
+        pos = torch.arange(words.numel(), dtype=torch.int64, device=words.device)
+        weights = pos * _DIGEST_MUL + _DIGEST_ADD
+        weights |= 1
+        d = torch.stack([words.sum(), (words * weights).sum()])
+    return (t,) + tuple(int(v) for v in d.cpu())
+
+
+def _keep_result(lat, keep):
+    """What a finished job hands back besides its diagnostics."""
+    if keep == "digest":
+        return {"digest": state_digest(lat)}
+    if keep == "state":
+        raw, t = raw_state(lat)
+        with torch.cuda.stream(lat.stream):
+            host = raw.cpu()
+        return {"digest": (t,), "state": host}
+    if keep == "fields":
+        with torch.cuda.stream(lat.stream):
+            return {"fields": tuple(a.cpu().numpy() for a in lat.moments())}
+    if keep in (None, "none"):
+        return {}
+    raise ValueError(f"keep must be None, 'digest', 'state' or 'fields', not {keep!r}")
+
+
 def percentile(xs, q):
     if not xs:
         return float("nan")
@@ -87,22 +151,64 @@ def percentile(xs, q):
     return s[lo] + (s[hi] - s[lo]) * (k - lo)
 
 
+# lattice updates per second the admission policy assumes for one job's
+# estimated service time
+SERVICE_LUPS_ESTIMATE = 2.5e11
+# a queued job is "aged" once it has waited AGE_FIXED_S + AGE_FACTOR times its
+# estimated service time
+AGE_FIXED_S = 0.05
+AGE_FACTOR = 0.5
+
+
+def service_estimate(spec):
+    """Seconds the job would take alone at SERVICE_LUPS_ESTIMATE."""
+    return spec.nx * spec.ny * spec.steps / SERVICE_LUPS_ESTIMATE
+
+
+def is_aged(spec, now):
+    return now - spec.arrival >= AGE_FIXED_S + AGE_FACTOR * service_estimate(spec)
+
+
+def order_queue(queue, policy, now):
+    """The queue in admission order for `policy` at time `now` (seconds of
+    the trace's clock): "fifo" by arrival; "sjf" by work (cells x steps);
+    "aged" shortest job first, except that aged jobs (waited at least
+    AGE_FIXED_S + AGE_FACTOR x their estimated service time) go first, in
+    arrival order.  With the server's head blocking, an aged job at the head
+    holds back every job behind it until it fits, so its wait is bounded by
+    its ageing time plus the time the admitted jobs take to free its room."""
+    if policy == "fifo":
+        return sorted(queue, key=lambda s: (s.arrival, s.tag))
+    if policy == "sjf":
+        return sorted(queue, key=lambda s: (s.nx * s.ny * s.steps, s.arrival, s.tag))
+    if policy == "aged":
+        return sorted(queue, key=lambda s: (0, s.arrival, s.tag) if is_aged(s, now)
+                      else (1, s.nx * s.ny * s.steps, s.arrival, s.tag))
+    raise ValueError(f"policy must be 'aged', 'sjf' or 'fifo', not {policy!r}")
+
+
 class Server:
-    """policy: "sjf" admits the queued job with the least work (cells x steps)
-    first, "fifo" in arrival order.  max_active_cells caps the cells being
-    advanced at once (enough to fill the GPU; more only stretches every job's
-    latency), in addition to the HBM budget and the member slots."""
+    """policy: "aged" (default) admits the queued job with the least work
+    (cells x steps) first unless a job has aged (see order_queue), "sjf" the
+    one with the least work, "fifo" in arrival order.  max_active_cells caps the cells being advanced
+    at once (enough to fill the GPU; more only stretches every job's
+    latency), in addition to the HBM budget and the member slots.  keep:
+    what each JobResult carries besides the diagnostics (None, "digest",
+    "state" or "fields")."""
 
     def __init__(self, hbm_budget_bytes, max_members=256, max_tiles=1 << 20, chunk_ms=10.0,
-                 device="cuda:0", screen=False, tune=False, policy="sjf", max_active_cells=1 << 25,
-                 tile_cells=512):
+                 device="cuda:0", screen=False, tune=False, policy="aged", max_active_cells=1 << 25,
+                 tile_cells=512, keep=None):
         self.device = torch.device(device)
         self.budget = int(hbm_budget_bytes)
         self.pool = Pool(max_members=max_members, max_tiles=max_tiles, device=self.device)
         self.pool.set_shape(tile_cells=tile_cells, block=512, grid=4096, graph_steps=256)
         self.max_members = max_members
         self.chunk_ms = chunk_ms
+        if policy not in ("aged", "sjf", "fifo"):
+            raise ValueError(f"policy must be 'aged', 'sjf' or 'fifo', not {policy!r}")
         self.policy = policy
+        self.keep = keep
         self.max_active_cells = max_active_cells
         self.screen = screen
         self.tune = tune
@@ -133,8 +239,8 @@ class Server:
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
             # admission by HBM budget, member slots and the active-cells cap
-            if self.policy == "sjf" and len(queue) > 1:
-                queue = collections.deque(sorted(queue, key=lambda s: s.nx * s.ny * s.steps))
+            if len(queue) > 1:
+                queue = collections.deque(order_queue(queue, self.policy, now))
             while queue:
                 spec = queue[0]
                 need = footprint(spec)
@@ -171,9 +277,10 @@ class Server:
             for lat in finished:
                 spec, admitted, need, _ = active.pop(id(lat))
                 status, diag = lat.diagnostics()
+                kept = _keep_result(lat, self.keep)
                 done = time.perf_counter() - t0
                 results.append(JobResult(spec.tag, spec.arrival, admitted, done, spec.nx, spec.ny, spec.steps,
-                                         spec.storage, diag, status))
+                                         spec.storage, diag, status, **kept))
                 lat.close()
                 self.used -= need
             if not active and not queue and pending:
@@ -186,8 +293,9 @@ class Server:
         self.pool.close()
 
 
-def run_plain(trace, device="cuda:0") -> List[JobResult]:
-    """One job at a time in arrival order, one plain launch per step."""
+def run_plain(trace, device="cuda:0", keep=None) -> List[JobResult]:
+    """One job at a time in arrival order, each with its lattice's default
+    launch shape (several steps per launch from 2^22 cells, else one)."""
     results = []
     t0 = time.perf_counter()
     for spec in sorted(trace, key=lambda s: s.arrival):
@@ -198,9 +306,10 @@ def run_plain(trace, device="cuda:0") -> List[JobResult]:
         lat = _new_lattice(spec, device)
         lat.step(spec.steps)
         status, diag = lat.diagnostics()
+        kept = _keep_result(lat, keep)
         done = time.perf_counter() - t0
         results.append(JobResult(spec.tag, spec.arrival, admitted, done, spec.nx, spec.ny, spec.steps,
-                                 spec.storage, diag, status))
+                                 spec.storage, diag, status, **kept))
         lat.close()
     return results
 
@@ -210,6 +319,7 @@ def summarize(results: List[JobResult]):
     lups = sum(r.nx * r.ny * r.steps for r in results)
     span = max(r.done for r in results) - min(r.arrival for r in results) if results else float("nan")
     return {"jobs": len(results), "p50_s": round(percentile(lat, 50), 4), "p99_s": round(percentile(lat, 99), 4),
+            "max_s": round(max(lat), 4) if lat else None,
             "mean_s": round(sum(lat) / max(1, len(lat)), 4), "makespan_s": round(span, 4),
             "aggregate_mlups": round(lups / span / 1e6, 1) if span > 0 else None,
             "nonfinite_jobs": sum(1 for r in results if r.status != 0)}

@@ -66,7 +66,29 @@ def test_pool_roofline_bound_follows_the_steps_per_launch():
     assert multi["bound"] == "alu" and multi["ops_per_update"] == bench.ALG_OPS_PER_LU
     assert multi["algorithmic_ops_per_launch"] == bench.ALG_OPS_PER_LU * cells * 7
     assert abs(multi["achieved"] - bench.ALG_OPS_PER_LU * cells * 7 / (us * 1e-6) / 1e12) < 0.01
+    # with the steps actually run given (67 steps in 10 launches of at most
+    # 7), the operations are those of 67 steps, not 70
+    part = bench.pool_roofline(7, cells, launches, ms, steps=67)
+    assert part["algorithmic_ops_timed"] == bench.ALG_OPS_PER_LU * cells * 67
+    assert abs(part["achieved"] - bench.ALG_OPS_PER_LU * cells * 67 / (ms * 1e-3) / 1e12) < 0.01
     assert abs(multi["peak"] - 39.32) < 0.01 and 0 < multi["frac"] < 1
     assert multi["hbm"]["achieved"] == one["achieved"]
     # the FP64 vector peak is half the FP32 one
     assert bench.ALU_PEAK["f64"] * 2 == bench.ALU_PEAK["f32"]
+
+
+def test_pool_member_launches_replays_the_chunking():
+    shape = bench.parse_pool_shape(bench.DEFAULT_POOL_SHAPE)
+    assert shape["steps_per_launch"] == 7 and shape["graph_steps"] == 256
+    # 500 steps: chunks 224, 224, 28, 14, 7 (seven-step launches) and one
+    # three-step pass
+    assert bench.pool_member_launches(shape, 500) == 32 + 32 + 4 + 2 + 1 + 1
+    assert bench.pool_member_launches(shape, 7) == 1
+    assert bench.pool_member_launches(shape, 3) == 1
+    one = dict(shape, steps_per_launch=1)
+    assert bench.pool_member_launches(one, 37) == 37
+
+
+def test_cpu_model_is_read_or_none():
+    m = bench.cpu_model()
+    assert m is None or (isinstance(m, str) and m)

@@ -286,3 +286,52 @@ def test_unstable_relaxation_set_blows_up_in_the_oracle():
     rho, ux, uy = lbm_inputs.gaussian_pulse(64, 64, 1e-3, 4.0)
     f = oracle.run(oracle.init(rho, ux, uy), s, 600)
     assert not np.all(np.isfinite(f)) or np.max(np.abs(f)) > 1e3
+
+
+def test_moments_of_single_population_cells():
+    # Sec. 2.1, Eq. q-macro: rho = sum_i f_i and rho u = sum_i v_i f_i.  A cell
+    # holding mass a in population i alone has density a and moves with that
+    # population's lattice velocity v_i exactly: a missing 1/rho (a != 1), a
+    # swapped or mis-signed velocity component, or a population left out of a
+    # sum fails here.
+    cx, cy = oracle.velocities()
+    a = np.array([0.5, 1.0, 2.0, 3.25])
+    for i in range(9):
+        f = np.zeros((9, 1, a.size))
+        f[i, 0, :] = a
+        rho, ux, uy = oracle.moments(f)
+        assert np.array_equal(rho[0], a)
+        assert np.array_equal(ux[0], np.full(a.size, float(cx[i])))
+        assert np.array_equal(uy[0], np.full(a.size, float(cy[i])))
+
+
+def test_moments_of_two_population_cell_weigh_by_mass():
+    # Two populations: rho u = a v_i + b v_j, divided by rho = a + b.
+    cx, cy = oracle.velocities()
+    f = np.zeros((9, 1, 1))
+    f[1, 0, 0], f[6, 0, 0] = 3.0, 1.0          # (1,0) with mass 3, (-1,1) with mass 1
+    rho, ux, uy = oracle.moments(f)
+    jx = 3.0 * cx[1] + 1.0 * cx[6]
+    jy = 3.0 * cy[1] + 1.0 * cy[6]
+    assert (jx, jy) == (2, 1)                   # the D2Q9 directions of those populations
+    assert rho[0, 0] == 4.0 and ux[0, 0] == 0.5 and uy[0, 0] == 0.25
+
+
+def test_moments_of_textbook_equilibrium_are_its_density_and_velocity():
+    # The textbook quadratic f^eq (Qian et al.) has zeroth moment rho and first
+    # moment rho u exactly (closed-form lattice sums), so the readback of
+    # random equilibrium fields must return those fields to a few ulps.
+    rng = np.random.default_rng(7)
+    ny, nx = 5, 6
+    rho = 1.0 + 0.2 * rng.standard_normal((ny, nx))
+    ux = 0.1 * rng.standard_normal((ny, nx))
+    uy = 0.1 * rng.standard_normal((ny, nx))
+    f = np.stack([feq_textbook(rho, ux, uy)[i] for i in range(9)])
+    r, u, v = oracle.moments(f)
+    assert np.max(np.abs(r - rho)) < 8e-16
+    assert np.max(np.abs(u - ux)) < 8e-16
+    assert np.max(np.abs(v - uy)) < 8e-16
+    # and the same through the oracle's own initialisation
+    r2, u2, v2 = oracle.moments(oracle.init(rho, ux, uy))
+    assert np.max(np.abs(r2 - rho)) < 8e-16
+    assert np.max(np.abs(u2 - ux)) < 8e-16 and np.max(np.abs(v2 - uy)) < 8e-16
