@@ -37,7 +37,8 @@ METRIC = "MLUPS & % HBM roofline (D2Q9 MRT, 1 GPU); served p50/p99 vs plain at e
 STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 
 
-KERNEL_SOURCES = ("lbm_device.hpp", "lbm_kernels.hip")     # the files that define the device code
+KERNEL_SOURCES = ("lbm_device.hpp", "lbm_step_common.hpp", "lbm_kernels.hip", "lbm_multi_f32.hip",
+                  "lbm_multi_f64.hip", "lbm_multi_f16.hip", "lbm_multi_bf16.hip")   # the files that define the device code
 
 
 def kernel_source_hash():

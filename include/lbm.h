@@ -235,7 +235,9 @@ LBM_API lbm_status lbm_write_populations(lbm_lattice *lat, const double *dev_f);
 LBM_API lbm_status lbm_set_node_equilibrium(lbm_lattice *lat, int32_t x, int32_t y, double rho, double ux,
                                             double uy);
 
-/* Bytes of the raw state (the current buffer in its storage type). */
+/* Bytes of the raw state: the current buffer in its storage type, laid out
+ * [9][ny][pitch] with pitch = nx rounded up to 64 elements (the values of
+ * columns nx..pitch-1 are unspecified). */
 LBM_API size_t lbm_state_bytes(const lbm_lattice *lat);
 /* Bitwise checkpoint of the raw state into / from a device buffer of
  * lbm_state_bytes bytes; load also sets t.  Enqueued. */

@@ -1,4 +1,10 @@
-"""Builds the HIP library ``liblbm.so`` for gfx950 with hipcc (in-tree)."""
+"""Builds the HIP library ``liblbm.so`` for gfx950 with hipcc (in-tree).
+
+Each source is compiled to its own object in parallel (each object carries
+its own gfx950 code object), then the objects are linked into the shared
+library."""
+import concurrent.futures
+import hashlib
 import os
 import subprocess
 import sys
@@ -6,11 +12,14 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_kernels.hip", "lbm_api.hip", "lbm_pool.hip", "lbm_source.hip"]
+OBJDIR = os.path.join(os.path.dirname(HERE), "_build", "lbm")
+SOURCES = ["lbm_multi_f32.hip", "lbm_multi_f64.hip", "lbm_multi_f16.hip", "lbm_multi_bf16.hip", "lbm_kernels.hip",
+           "lbm_api.hip", "lbm_pool.hip", "lbm_source.hip"]
+HEADERS = ["lbm_device.hpp", "lbm_internal.hpp", "lbm_step_common.hpp", os.path.join("..", "..", "include", "lbm.h")]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
-    "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
     "-Wall", "-Wno-unused-function",
     # every product and sum rounds separately: results do not depend on how
     # the compiler schedules a kernel, so all launch shapes and the batched
@@ -22,10 +31,39 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, extra=()) -> str:
+def _digest(src, cmd):
+    h = hashlib.sha256(" ".join(cmd).encode())
+    for name in [src] + HEADERS:
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def build(verbose: bool = False, extra=(), incremental: bool = False) -> str:
+    """Compiles every source and links the library.  incremental=True (for
+    development only) reuses an object whose source, headers and command are
+    unchanged."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    cmd = [hipcc] + FLAGS + list(extra) + srcs + ["-o", LIB + ".tmp"]
+    os.makedirs(OBJDIR, exist_ok=True)
+
+    def compile_one(src):
+        obj = os.path.join(OBJDIR, src.replace(".hip", ".o"))
+        cmd = [hipcc] + FLAGS + list(extra) + ["-c", os.path.join(CSRC, src), "-o", obj + ".tmp"]
+        stamp = obj + ".sha256"
+        dig = _digest(src, cmd)
+        if incremental and os.path.exists(obj) and os.path.exists(stamp) and open(stamp).read() == dig:
+            return obj
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(obj + ".tmp", obj)
+        with open(stamp, "w") as fh:
+            fh.write(dig)
+        return obj
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
+    cmd = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC"] + objs + ["-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
@@ -34,4 +72,4 @@ def build(verbose: bool = False, extra=()) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv)

@@ -122,7 +122,8 @@ def state_digest(lat):
         weights = pos * _DIGEST_MUL + _DIGEST_ADD
         weights |= 1
         d = torch.stack([words.sum(), (words * weights).sum()])
-    return (t,) + tuple(int(v) for v in d.cpu())
+        host = d.cpu()                  # ordered after the sums on the lattice's stream
+    return (t,) + tuple(int(v) for v in host)
 
 
 def _keep_result(lat, keep):

@@ -1,7 +1,9 @@
 """Linear (von Neumann) stability screen for relaxation sets, used to admit
 simulation jobs: a set is admitted when max |eig G(k)| <= 1 + tol on an
 nk x nk wavenumber grid (Sec. 4.1; G(k) as in ``vonneumann``)."""
-from . import vonneumann
+import numpy as np
+
+from . import _lib, vonneumann
 
 
 def spectral_radius(s_e, s_eps, s_q, s_nu, U=0.0, V=0.0, nk=32):
@@ -9,7 +11,11 @@ def spectral_radius(s_e, s_eps, s_q, s_nu, U=0.0, V=0.0, nk=32):
 
 
 def s_from_nu(nu):
-    return 1.0 / (3.0 * nu + 0.5)
+    """s_nu of a lattice viscosity nu (scalar or array): the library's own
+    conversion, lbm_s_from_nu."""
+    if np.ndim(nu) == 0:
+        return _lib.lbm_s_from_nu(float(nu))
+    return np.vectorize(_lib.lbm_s_from_nu, otypes=[np.float64])(np.asarray(nu, dtype=np.float64))
 
 
 def rates(relax):

@@ -47,10 +47,10 @@ def test_bench_line_for_the_several_steps_default(steps):
     # over that kernel's own average launch time
     assert r["algorithmic_ops_per_launch"] == ALG_OPS_PER_LU * 4096 * 4096 * T
     assert abs(r["achieved"] - r["algorithmic_ops_per_launch"] / (r["avg_launch_us"] * 1e-6) / 1e12) < 0.02
-    # the dominant kernel is at least as fast per step as the region with its
-    # shorter left-over launch, and within a few per cent of it
+    # the dominant kernel is at least as fast per step as the whole region:
+    # the left-over launch (steps % T steps) reads and writes every
+    # population once like a full launch, for fewer steps
     assert r["frac"] >= reg["frac"] * 0.97
-    assert r["frac"] <= reg["frac"] * 1.10
     # one-pass equivalent: 72 B per update at the line's update rate
     ope = r["one_pass_equiv"]
     assert ope["bytes_per_update"] == 72
