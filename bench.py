@@ -94,9 +94,11 @@ def read_traffic(workload, storage, launch):
         return None
 
 
-# Launch shapes lbm_tune selected for the 4096^2 wave workload on MI355X
-# (variants 11, 12 and 13: five, six and seven steps per pass); --tune searches again.
-DEFAULT_LAUNCH = {"f32": "13,64,4,168,1,2", "f16": "11,64,4,64,1,12", "bf16": "11,64,4,64,1,8",
+# Launch shapes measured fastest for the 4096^2 wave workload on MI355X
+# (variants 11, 12 and 13: five, six and seven steps per pass; flag 32: the
+# workgroup-shared halo); the library's defaults for this lattice; --tune
+# searches again.
+DEFAULT_LAUNCH = {"f32": "13,64,4,92,1,32", "f16": "12,64,4,69,1,34", "bf16": "11,64,4,69,1,40",
                   "f64": "13,64,4,168,1,12"}
 
 

@@ -102,9 +102,11 @@ typedef struct lbm_lattice lbm_lattice;
 
 /* Launch shape of the fused step kernel (chosen by lbm_tune or set by hand;
  * a new lattice of at least 2^22 cells starts with a several-steps shape
- * by storage type: FP32 {13, 64, 4, 168, 1, 2}, FP16 {11, 64, 4, 64, 1, 12},
- * BF16 {11, 64, 4, 64, 1, 8}, FP64 {13, 64, 4, 168, 1, 12}; a smaller one
- * with {0, 64, 4, 1, 1, 0}).
+ * by storage type: FP32 {13, 64, 4, R, 1, 32}, FP16 {12, 64, 4, R, 1, 34},
+ * BF16 {11, 64, 4, R, 1, 40} (workgroup-shared halo, R chosen from the
+ * lattice size so that three (FP32) or four (FP16, BF16) workgroups per
+ * compute unit cover the lattice in one round: 92, 69, 69 rows on 4096^2),
+ * FP64 {13, 64, 4, 168, 1, 12}; a smaller one with {0, 64, 4, 1, 1, 0}).
  *   variant   0 = one cell per lane (nine direct loads),
  *             1, 2, 3 = 2, 4, 8 consecutive cells per lane (aligned vector
  *             loads, x-shift by cross-lane exchange; needs nx % 2^variant == 0
@@ -138,7 +140,14 @@ typedef struct lbm_lattice lbm_lattice;
  *             rows ahead; bit 4 (variants 9-12 only, not with bit 0):
  *             skewed pipeline, in which stage p works two rows behind stage
  *             p-1 instead of one, so that the T collisions of a row
- *             iteration do not depend on each other.
+ *             iteration do not depend on each other; bit 5 (variants
+ *             10-13, FP32/FP16/BF16 storage, flags 32, 34 or 40 only):
+ *             workgroup-shared halo -- the block_y waves of a workgroup
+ *             own one strip of 64 block_y - 2(T-1) columns (rounded as
+ *             above) and pass the values a stage takes from the
+ *             neighbouring column through LDS (with a workgroup barrier per
+ *             stage), so that only the workgroup's outer edges recompute a
+ *             halo.
  * Every shape produces bit-identical results. */
 typedef struct lbm_launch {
     int32_t variant;
@@ -195,7 +204,8 @@ LBM_API lbm_status lbm_init_equilibrium(lbm_lattice *lat, const double *rho, con
  * l-mrt-lbs).  Enqueued.  LBM_E_STATE before init.  With a shape of T > 1
  * steps per launch: n / T launches of it, then the r = n % T remaining
  * steps in one launch of the same shape with r steps per pass (variant
- * 6 + r) when r >= 2 and that shape is supported, else r one-step
+ * 6 + r) when r >= 2 and that shape is supported (for a shared-halo shape
+ * with r < 4: the same with one wave per strip and flags 2), else r one-step
  * launches; every split gives bit-identical results. */
 LBM_API lbm_status lbm_step(lbm_lattice *lat, int64_t n);
 /* Kernel launches lbm_step(lat, n) makes with the current shapes; -1 if

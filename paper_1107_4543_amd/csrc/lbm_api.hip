@@ -99,12 +99,45 @@ lbm_launch default_single(const View &)
     return c;
 }
 
+// Compute units of the current device (queried once per device; 256 on
+// MI355X).
+int device_cus()
+{
+    static int cus[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cus[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
+
+// Segment rows of a shared-halo shape (T steps, waves per workgroup) that
+// give about per_cu workgroups per compute unit in one round: strips of
+// multi_strip_cols columns, as many segments as the resident workgroups
+// allow, each as tall as the lattice then needs.  Taller segments repeat
+// fewer of the pipeline's 2(T-1) start-up rows; one round keeps every
+// compute unit equally loaded.
+int wg_rows(const View &v, int T, int waves, int per_cu)
+{
+    const int cols = lbm::multi_strip_cols(T, (int)lbm::storage_bytes(v.storage), 64 * waves);
+    const int tiles_x = (v.nx + cols - 1) / cols;
+    const int segs = std::max(1, per_cu * device_cus() / tiles_x);
+    return std::max(1, std::min(4096, (v.ny + segs - 1) / segs));
+}
+
 // Large lattices (>= 2^22 cells): several steps per launch with the shape
-// measured fastest for the storage type on 4096^2 and 8192^2 lattices
-// (variant, waves per workgroup, segment rows, flags): FP32 (13, 4, 168, 2),
-// FP16 (11, 4, 64, 12), BF16 (11, 4, 64, 8), FP64 (13, 4, 168, 12).  Smaller
-// lattices offer too few strip segments to keep the GPU busy through the
-// pipeline and keep the one-step shape.
+// measured fastest for the storage type on the 4096^2 wave workload: for
+// 32- and 16-bit storage the workgroup-shared halo with four waves per
+// workgroup -- FP32: T = 7, loads not ahead (flags 32), segments for three
+// workgroups per compute unit (92 rows on 4096^2); FP16: T = 6, loads one row
+// ahead (34), four per compute unit (69 rows); BF16: T = 5, two rows ahead
+// (40), four per compute unit (69 rows) -- and for FP64 storage T = 7 with
+// one wave per strip (13, 4, 168, 12).  Smaller lattices offer too few
+// strip segments to keep the GPU busy through the pipeline and keep the
+// one-step shape.
 lbm_launch default_launch(const View &v)
 {
     if ((int64_t)v.nx * v.ny < ((int64_t)1 << 22)) return default_single(v);
@@ -112,9 +145,9 @@ lbm_launch default_launch(const View &v)
     c.block_x = 64;
     c.xcd_remap = 1;
     switch (v.storage) {
-    case LBM_STORE_F32: c.variant = 13; c.block_y = 4; c.rows = 168; c.flags = 2; break;
-    case LBM_STORE_F16: c.variant = 11; c.block_y = 4; c.rows = 64; c.flags = 12; break;
-    case LBM_STORE_BF16: c.variant = 11; c.block_y = 4; c.rows = 64; c.flags = 8; break;
+    case LBM_STORE_F32: c.variant = 13; c.block_y = 4; c.flags = 32; c.rows = wg_rows(v, 7, 4, 3); break;
+    case LBM_STORE_F16: c.variant = 12; c.block_y = 4; c.flags = 34; c.rows = wg_rows(v, 6, 4, 4); break;
+    case LBM_STORE_BF16: c.variant = 11; c.block_y = 4; c.flags = 40; c.rows = wg_rows(v, 5, 4, 4); break;
     default: c.variant = 13; c.block_y = 4; c.rows = 168; c.flags = 12; break;
     }
     return c;
@@ -158,10 +191,24 @@ std::vector<lbm_launch> variant_candidates(const View &v, const lbm_launch &best
     return out;
 }
 
-// Tuner stage 3: shapes that advance several steps per launch.
+// Tuner stage 3: shapes that advance several steps per launch (one wave
+// per strip, and the workgroup-shared halo with segments sized for two to
+// four workgroups per compute unit).
 std::vector<lbm_launch> multi_candidates(const View &v)
 {
     std::vector<lbm_launch> out;
+    for (int var = 10; var <= 13; ++var)
+        for (int flags : {32, 34, 40})
+            for (int per_cu : {2, 3, 4}) {
+                lbm_launch c{};
+                c.variant = var;
+                c.block_x = 64;
+                c.block_y = 4;
+                c.rows = wg_rows(v, var - 6, 4, per_cu);
+                c.xcd_remap = 1;
+                c.flags = flags;
+                if (lbm::step_shape_supported(v, c)) out.push_back(c);
+            }
     for (int var = 8; var <= 13; ++var)
         for (int by : {1, 4})
             for (int rows : {32, 64, 168, 176, 256})
@@ -351,13 +398,19 @@ namespace {
 
 // The r < T steps left after the T-step launches of lbm_step: one launch of
 // the current shape with r steps per pass when r >= 2 (then T > 2 and the
-// current shape is a several-steps one) and that shape is supported (*ok),
-// else r one-step launches.
+// current shape is a several-steps one) and that shape is supported (*ok);
+// a shared-halo shape whose r-step version does not exist (r < 4) takes
+// r steps with one wave per strip, loads one row ahead (flags 2); else r
+// one-step launches.
 lbm_launch remainder_shape(const lbm_lattice *lat, int r, bool *ok)
 {
     lbm_launch c = lat->launch;
     c.variant = 6 + r;
     *ok = r >= 2 && lbm::step_shape_supported(lat->v, c);
+    if (!*ok && r >= 2 && (c.flags & lbm::kWgHalo)) {
+        c.flags = 2;
+        *ok = lbm::step_shape_supported(lat->v, c);
+    }
     return c;
 }
 

@@ -22,6 +22,8 @@ struct View {
     double scale, inv_scale;  // 2^p, 2^-p
 };
 
+constexpr int kWgHalo = 32;        // launch-flags bit of the workgroup-shared halo (variants 10-13)
+constexpr int kWgMaxWaves = 4;     // waves per workgroup it supports
 constexpr int kRedBlocks = 512;    // blocks of the two-pass reductions
 constexpr int kRedWidth = 20;      // max doubles per block partial
 constexpr size_t kScratchBytes = (size_t)kRedBlocks * kRedWidth * sizeof(double) + 64 * sizeof(double);
@@ -30,8 +32,10 @@ size_t storage_bytes(int32_t storage);
 bool step_shape_supported(const View &v, const lbm_launch &cfg);
 // Steps one launch of this shape advances (several-steps-per-pass variants).
 int steps_per_launch(const lbm_launch &cfg);
-// Output columns of a T-step strip for a storage element of elem_bytes.
-int multi_strip_cols(int T, int elem_bytes);
+// Output columns of a T-step strip run by `lanes` lanes (one wave: 64; a
+// workgroup with the shared halo: 64 per wave) for a storage element of
+// elem_bytes.
+int multi_strip_cols(int T, int elem_bytes, int lanes = 64);
 
 hipError_t launch_step(const View &v, const void *src, void *dst, const lbm_launch &cfg,
                        hipStream_t st);

@@ -669,14 +669,17 @@ hipError_t launch_step_typed(const View &v, const void *src, void *dst, const lb
     a.nwaves = 0;
     a.out_cols = 0;
     if (cfg.variant >= 8) {
-        // strips of multi_strip_cols output columns, segments of `rows` rows, one wave each
+        // strips of multi_strip_cols output columns, segments of `rows` rows,
+        // one wave each (with the shared halo: one workgroup of block_y
+        // waves each, strips as wide as its lanes allow)
         const int T = cfg.variant - 6;
-        a.out_cols = multi_strip_cols(T, (int)sizeof(typename Store<S>::raw));
+        const bool wg = (cfg.flags & kWgHalo) != 0;
+        a.out_cols = multi_strip_cols(T, (int)sizeof(typename Store<S>::raw), wg ? 64 * cfg.block_y : 64);
         a.tiles_x = (v.nx + a.out_cols - 1) / a.out_cols;
         a.tile_h = cfg.rows;
         const int segs = (v.ny + cfg.rows - 1) / cfg.rows;
         a.nwaves = a.tiles_x * segs;
-        a.nblocks = (a.nwaves + cfg.block_y - 1) / cfg.block_y;
+        a.nblocks = wg ? a.nwaves : (a.nwaves + cfg.block_y - 1) / cfg.block_y;
     }
     const dim3 grid(a.nblocks), block(cfg.block_x, cfg.block_y);
     if (cfg.variant >= 8) return launch_multi<S, C>(a, grid, block, cfg.variant - 6, cfg.flags, st);
@@ -806,9 +809,9 @@ int steps_per_launch(const lbm_launch &cfg) { return cfg.variant >= 8 && cfg.var
 // that neighbouring strips' row stores meet on sector boundaries (measured:
 // 58 -> 56 columns at T = 4 is +17 % for FP32 and FP64 storage; larger cuts
 // cost more lanes than they gain).
-int multi_strip_cols(int T, int elem_bytes)
+int multi_strip_cols(int T, int elem_bytes, int lanes)
 {
-    const int raw = 64 - 2 * (T - 1);
+    const int raw = lanes - 2 * (T - 1);
     for (int bytes : {32, 16}) {
         const int a = elem_bytes >= bytes ? 1 : bytes / elem_bytes;
         const int aligned = raw - raw % a;
@@ -823,6 +826,15 @@ bool step_shape_supported(const View &v, const lbm_launch &cfg)
         // several steps per pass: one wave per strip and segment
         if (cfg.variant >= 11 && (cfg.flags & 1)) return false;   // T = 5, 6, 7: no non-temporal loads
         if (cfg.variant == 13 && (cfg.flags & 16)) return false;  // T = 7: plain pipeline only
+        if (cfg.flags & kWgHalo) {
+            // shared halo: T = 4 .. 7, flags 32, 34 or 40 (plain pipeline,
+            // no shuffles, loads one or two rows ahead or none), 32- or
+            // 16-bit wide values (FP32 arithmetic on the stored type)
+            if (cfg.variant < 10 || v.storage == LBM_STORE_F64) return false;
+            if (cfg.flags != kWgHalo && cfg.flags != (kWgHalo | 2) && cfg.flags != (kWgHalo | 8)) return false;
+            return cfg.block_x == 64 && cfg.block_y >= 1 && cfg.block_y <= kWgMaxWaves && cfg.rows >= 1 &&
+                   cfg.rows <= 4096 && (cfg.xcd_remap == 0 || cfg.xcd_remap == 1);
+        }
         return cfg.block_x == 64 && cfg.block_y >= 1 && cfg.block_y <= 4 && cfg.rows >= 1 &&
                cfg.rows <= 4096 && (cfg.xcd_remap == 0 || cfg.xcd_remap == 1) && cfg.flags >= 0 &&
                cfg.flags <= 29 && !((cfg.flags & 8) && (cfg.flags & 2)) &&

@@ -10,9 +10,9 @@ namespace {
 template <typename S, typename C>
 hipError_t launch_multi_impl(const StepArgs<C> &a, dim3 grid, dim3 block, int T, int flags, hipStream_t st)
 {
-    switch ((T - 2) * 32 + flags) {
+    switch ((T - 2) * 64 + flags) {
 #define LBM_MULTI(T_, F_)                                                                    \
-    case (T_ - 2) * 32 + F_: hipLaunchKernelGGL((k_step_multi<S, C, T_, F_>), grid, block, 0, st, a); break;
+    case (T_ - 2) * 64 + F_: hipLaunchKernelGGL((k_step_multi<S, C, T_, F_>), grid, block, 0, st, a); break;
 #define LBM_MULTI_T(T_) LBM_MULTI(T_, 0) LBM_MULTI(T_, 1) LBM_MULTI(T_, 2) LBM_MULTI(T_, 3) \
                         LBM_MULTI(T_, 4) LBM_MULTI(T_, 5) LBM_MULTI(T_, 6) LBM_MULTI(T_, 7) \
                         LBM_MULTI(T_, 8) LBM_MULTI(T_, 9) LBM_MULTI(T_, 12) LBM_MULTI(T_, 13)

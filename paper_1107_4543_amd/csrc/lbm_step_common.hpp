@@ -318,32 +318,72 @@ __device__ __forceinline__ bool one_resource(int64_t plane)
     return (uint64_t)plane * sizeof(typename Store<S>::raw) * 9 <= 0xFFFFFFFFull;
 }
 
-// T steps of the strip whose cols output columns start at x0 (cols <=
-// 64 - 2(T-1)), rows y0 .. y0+len-1 of one lattice, by the calling wave
-// (threadIdx.x = lane; lane T-1 holds column x0).
+// Workgroup-shared halo (FLAGS bit 5): the waves of a workgroup cover
+// adjacent 64-column pieces of one strip and walk its rows in step.  Each
+// stage's output values that the next stage takes from the column to the
+// left or right (populations 1, 3, 5, 6, 7, 8) go through LDS instead of a
+// cross-lane shuffle: every lane writes them at its column of a
+// workgroup-wide row, a barrier, and every lane reads its neighbours' --
+// the edge lanes of a wave read the adjacent wave's.  Only the workgroup's
+// outer edges lose a column per stage, so a workgroup of W waves writes
+// 64 W - 2(T-1) columns instead of W (64 - 2(T-1)).  One buffer per stage
+// boundary suffices as long as a barrier separates every read of it from
+// its next write: boundary b > 0 is rewritten after boundary b - 1's
+// barrier of the next row, boundary 0 after the next stage's barrier of the
+// same row (every prologue row also starts with a barrier, for the rows
+// that run no second exchange).
+
+// T steps of the strip whose cols output columns start at x0, rows y0 ..
+// y0+len-1 of one lattice.  Without the shared halo the calling wave owns
+// the strip (threadIdx.x = lane; lane T-1 holds column x0; cols <= 64 -
+// 2(T-1)); with it the calling workgroup does (wave threadIdx.y holds
+// columns x0 - (T-1) + 64 threadIdx.y + lane; cols <= 64 blockDim.y -
+// 2(T-1)), and every wave of the workgroup must call with the same
+// arguments.
+// LDS of the shared-halo exchange: stage boundary b (output of stage b),
+// value k (populations 1, 3, 5, 6, 7, 8), column of the workgroup's lanes.
+constexpr int kWgXchCols = 64 * kWgMaxWaves;
+template <typename S, int T>
+struct WgExchange {
+    typename Store<S>::wide v[(T - 1) * 6 * kWgXchCols];
+};
+
 template <typename S, typename C, int T, int FLAGS, bool ONE_RSRC>
 __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *__restrict__ dst, int nx, int ny,
                                            int pitch, int64_t plane, const Relax<C> &relax, float scale,
-                                           float inv_scale, int x0, int cols, int y0, int len)
+                                           float inv_scale, int x0, int cols, int y0, int len,
+                                           WgExchange<S, T> *wgx = nullptr)
 {
     using R = typename Store<S>::raw;
     using W = typename Store<S>::wide;
     constexpr bool NT = (FLAGS & 1) != 0;
     constexpr bool DPP = (FLAGS & 4) != 0;
+    constexpr bool WG = (FLAGS & kWgHalo) != 0;
     // rows of stage-0 loads issued ahead of the row being collided
     constexpr int AHEAD = (FLAGS & 8) ? 2 : ((FLAGS & 2) ? 1 : 0);
     // skewed pipeline: stage p works on row r - 2p and reads only outputs of
     // earlier iterations, so the T collides of an iteration are independent
     constexpr bool SKEW = (FLAGS & 16) != 0;
     constexpr int LAG = SKEW ? 3 : 2;                   // iterations from one stage's start to the next
+    static_assert(!(WG && SKEW), "the workgroup-shared halo runs the plain pipeline");
     constexpr uint32_t E = sizeof(R);
     const int lane = threadIdx.x;
-    const int xl = x0 + lane - (T - 1);                 // unwrapped column
+    // column of this lane within the strip's lanes (the workgroup's with the
+    // shared halo, the wave's without)
+    const int lc = WG ? 64 * (int)threadIdx.y + lane : lane;
+    const int xl = x0 + lc - (T - 1);                   // unwrapped column
     const int c = wrap_mod(xl, nx);
     const uint32_t c0 = (uint32_t)c * E;
     const uint32_t cm = (uint32_t)((c == 0 ? nx : c) - 1) * E;
     const uint32_t cp = (uint32_t)((c + 1 == nx) ? 0 : c + 1) * E;
-    const bool writes = lane >= T - 1 && lane < T - 1 + cols && xl < nx;
+    const bool writes = lc >= T - 1 && lc < T - 1 + cols && xl < nx;
+    // shared-halo exchange rows (wgx, the kernel's LDS); the neighbour
+    // columns are clamped at the workgroup's edges (those lanes' results are
+    // not used)
+    constexpr int XW = kWgXchCols;
+    W *const xch = WG ? wgx->v : nullptr;
+    const int lanes = WG ? 64 * (int)blockDim.y : 64;
+    const int lcl = lc > 0 ? lc - 1 : 0, lcr = lc + 1 < lanes ? lc + 1 : lc;
     const uint64_t pb = (uint64_t)plane * E;
     const uint32_t rb = (uint32_t)pitch * E;
     const int iters = len + LAG * (T - 1);
@@ -424,33 +464,77 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
             gather_next(w);                             // row r
         }
         cell_update<S, C>(w, relax, scale, inv_scale);
+        if constexpr (WG) {
+            // Stage boundary 0 is written again at the start of every row,
+            // so a barrier must separate the previous row's reads of it
+            // from this row's writes.  A steady row has one after those
+            // reads (the next stage's exchange); a prologue row that runs
+            // stage 0 and 1 only (rows 0 and 1) has none, so the rows after
+            // them start with one.
+            if (!STEADY && j >= 1) __syncthreads();
+        }
 #pragma unroll
         for (int p = 1; p < T; ++p) {
             // w holds stage p-1's output, row r - p + 1
 #pragma unroll
             for (int i = 0; i < 9; ++i) w[i] = round_trip<S>(w[i]);
             W in[9];
-            const bool active = STEADY || j >= 2 * p;   // wave-uniform
-            if (active) {
-                in[0] = mid[p - 1][0];
-                in[1] = from_left<DPP>(mid[p - 1][1]);
-                in[3] = from_right<DPP>(mid[p - 1][2]);
-                in[2] = up[p - 1][0];
-                in[5] = from_left<DPP>(up[p - 1][1]);
-                in[6] = from_right<DPP>(up[p - 1][2]);
-                in[4] = w[4];
-                in[7] = from_right<DPP>(w[7]);
-                in[8] = from_left<DPP>(w[8]);
+            const bool active = STEADY || j >= 2 * p;   // wave-uniform (workgroup-uniform)
+            if constexpr (WG) {
+                // shifted once, where produced: mid and up keep the shifted
+                // populations 1, 3 and 5, 6 for the next two rows
+                W *xb = xch + (p - 1) * 6 * XW;
+                xb[0 * XW + lc] = w[1];
+                xb[1 * XW + lc] = w[3];
+                xb[2 * XW + lc] = w[5];
+                xb[3 * XW + lc] = w[6];
+                xb[4 * XW + lc] = w[7];
+                xb[5 * XW + lc] = w[8];
+                __syncthreads();
+                const W l1 = xb[0 * XW + lcl], r3 = xb[1 * XW + lcr], l5 = xb[2 * XW + lcl];
+                const W r6 = xb[3 * XW + lcr], r7 = xb[4 * XW + lcr], l8 = xb[5 * XW + lcl];
+                if (active) {
+                    in[0] = mid[p - 1][0];
+                    in[1] = mid[p - 1][1];
+                    in[3] = mid[p - 1][2];
+                    in[2] = up[p - 1][0];
+                    in[5] = up[p - 1][1];
+                    in[6] = up[p - 1][2];
+                    in[4] = w[4];
+                    in[7] = r7;
+                    in[8] = l8;
+                }
+                up[p - 1][0] = mid[p - 1][3];
+                up[p - 1][1] = mid[p - 1][4];
+                up[p - 1][2] = mid[p - 1][5];
+                mid[p - 1][0] = w[0];
+                mid[p - 1][1] = l1;
+                mid[p - 1][2] = r3;
+                mid[p - 1][3] = w[2];
+                mid[p - 1][4] = l5;
+                mid[p - 1][5] = r6;
+            } else {
+                if (active) {
+                    in[0] = mid[p - 1][0];
+                    in[1] = from_left<DPP>(mid[p - 1][1]);
+                    in[3] = from_right<DPP>(mid[p - 1][2]);
+                    in[2] = up[p - 1][0];
+                    in[5] = from_left<DPP>(up[p - 1][1]);
+                    in[6] = from_right<DPP>(up[p - 1][2]);
+                    in[4] = w[4];
+                    in[7] = from_right<DPP>(w[7]);
+                    in[8] = from_left<DPP>(w[8]);
+                }
+                up[p - 1][0] = mid[p - 1][3];
+                up[p - 1][1] = mid[p - 1][4];
+                up[p - 1][2] = mid[p - 1][5];
+                mid[p - 1][0] = w[0];
+                mid[p - 1][1] = w[1];
+                mid[p - 1][2] = w[3];
+                mid[p - 1][3] = w[2];
+                mid[p - 1][4] = w[5];
+                mid[p - 1][5] = w[6];
             }
-            up[p - 1][0] = mid[p - 1][3];
-            up[p - 1][1] = mid[p - 1][4];
-            up[p - 1][2] = mid[p - 1][5];
-            mid[p - 1][0] = w[0];
-            mid[p - 1][1] = w[1];
-            mid[p - 1][2] = w[3];
-            mid[p - 1][3] = w[2];
-            mid[p - 1][4] = w[5];
-            mid[p - 1][5] = w[6];
             if (!active) break;
 #pragma unroll
             for (int i = 0; i < 9; ++i) w[i] = in[i];
@@ -541,29 +625,40 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
     if (j < iters) step_row(j, std::true_type{}, ahead[0]);
 }
 
+// Waves per SIMD the register allocation of a several-steps kernel aims
+// for: with the shared halo (36 KB of LDS per workgroup at T = 7) four
+// workgroups of four waves fit a CU when a wave takes at most 128 VGPRs.
+template <int FLAGS>
+constexpr int multi_waves_per_eu() { return (FLAGS & kWgHalo) ? 4 : 1; }
+
 template <typename S, typename C, int T, int FLAGS>
-__global__ void __launch_bounds__(256) k_step_multi(StepArgs<C> a)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(multi_waves_per_eu<FLAGS>())))
+k_step_multi(StepArgs<C> a)
 {
     const int OUT = a.out_cols;
     int bid = blockIdx.x;
     if (a.xcd_remap) bid = remap_xcd(bid, a.nblocks);
-    // one wave per strip segment (blockDim.x is the wave size): the index
-    // is uniform across the wave, which readfirstlane states to the compiler
-    const int wave = __builtin_amdgcn_readfirstlane(bid * (int)blockDim.y + (int)threadIdx.y);
-    if (wave >= a.nwaves) return;                       // whole waves only
+    // one wave per strip segment (blockDim.x is the wave size), or with the
+    // shared halo one workgroup per strip segment: the index is uniform
+    // across the wave, which readfirstlane states to the compiler
+    const int wave = (FLAGS & kWgHalo) ? bid : __builtin_amdgcn_readfirstlane(bid * (int)blockDim.y + (int)threadIdx.y);
+    if (wave >= a.nwaves) return;                       // whole waves (workgroups) only
     const int strip = wave % a.tiles_x, seg = wave / a.tiles_x;
     const int y0 = seg * a.tile_h;
+    __shared__ WgExchange<S, (FLAGS & kWgHalo) ? T : 2> wgx;
     // one resource per buffer where it measured faster (FP32 storage: +2 %;
     // with 16-bit storage and in the pool it was slower), else per plane row
     if constexpr (std::is_same<S, float>::value) {
         if (one_resource<S>(a.plane)) {
             strip_pass<S, C, T, FLAGS, true>((const char *)a.src, (char *)a.dst, a.nx, a.ny, a.pitch, a.plane, a.r,
-                                             a.scale, a.inv_scale, strip * OUT, OUT, y0, min(a.tile_h, a.ny - y0));
+                                             a.scale, a.inv_scale, strip * OUT, OUT, y0, min(a.tile_h, a.ny - y0),
+                                             (WgExchange<S, T> *)&wgx);
             return;
         }
     }
     strip_pass<S, C, T, FLAGS, false>((const char *)a.src, (char *)a.dst, a.nx, a.ny, a.pitch, a.plane, a.r,
-                                      a.scale, a.inv_scale, strip * OUT, OUT, y0, min(a.tile_h, a.ny - y0));
+                                      a.scale, a.inv_scale, strip * OUT, OUT, y0, min(a.tile_h, a.ny - y0),
+                                      (WgExchange<S, T> *)&wgx);
 }
 
 template <typename C>

@@ -2,15 +2,16 @@
 directions: a 4096 x 4096 lattice with 16 seeded Gaussian pulses (fields
 that vary along x and y) on the mean flow u_x = 0.1 c_s with the Table 5
 group A rates, run with each storage type's recorded default launch shape
-(seven steps per pass for FP32, strips of 52 columns and 168-row segments),
+(the one bench.py times: for FP32 seven steps per pass, workgroups of four
+waves sharing their halo columns, strips of 244 columns and 92-row segments),
 compared with the FP64 oracle on sampled blocks.
 
 A cell's value after T steps depends only on cells within distance T, so the
 oracle run on a periodic window of side 2T + 1 + 2r reproduces a (2r + 1)^2
 block of the full run exactly (pinned on the CPU by
 test_window_run_reproduces_the_centre_of_a_larger_periodic_run).  The blocks
-straddle the places where the kernel's work is cut: strip edges (every 52
-columns), segment edges (every 168 rows) and the lattice's periodic wrap.
+straddle the places where the kernel's work is cut: strip edges, segment
+edges and the lattice's periodic wrap.
 Tolerances: FP32 within 1e-5 A on the density and 1e-5 A_u on the velocity;
 FP16 and BF16 storage within the rounding bound 3 u sqrt(T) A.
 """
@@ -18,6 +19,7 @@ import numpy as np
 import pytest
 import torch
 
+import bench
 import lbm_inputs
 import oracle
 
@@ -26,10 +28,13 @@ pytestmark = pytest.mark.gpu
 N = 4096
 T = 147                       # 21 seven-step launches
 R = 5                         # blocks of 11 x 11 cells
-# block centres: strip edge x = 52 k, segment edge y = 168 k, the corner
-# (periodic wrap in x and y), and an interior cell
-CENTRES = [(52 * 7, 168 * 3), (52 * 40 + 1, 168 * 12 - 1), (0, 0), (N - 1, 2000), (1234, 3210)]
-LAUNCH = {"f32": (13, 64, 4, 168, 1, 2), "f16": (11, 64, 4, 64, 1, 12), "bf16": (11, 64, 4, 64, 1, 8)}
+# block centres: strip edges (x = 244 k for the FP32 shape; 52 k of the
+# one-wave strips), segment edges (y = 92 k; 69 k for FP16/BF16), the corner
+# (periodic wrap in x and y), interior cells
+CENTRES = [(244 * 3, 92 * 5), (244 * 9 + 1, 69 * 12 - 1), (0, 0), (N - 1, 2000), (52 * 40, 168 * 12),
+           (1234, 3210)]
+# the launch shapes bench.py times (the recorded defaults for each storage type)
+LAUNCH = {k: tuple(int(x) for x in v.split(",")) for k, v in bench.DEFAULT_LAUNCH.items()}
 
 
 def _rates():
@@ -42,6 +47,7 @@ def workload():
     u0x = 0.1 * lbm_inputs.CS
     specs = lbm_inputs.random_pulse_specs(N, N, seed=77, count=16, amp_range=(1e-5, 1e-3))
     # put pulses on the sampled blocks so that every block sees a signal
+    assert len(specs) >= len(CENTRES)
     for k, (cx, cy) in enumerate(CENTRES):
         specs[k].cx, specs[k].cy = cx + 0.3, cy - 0.4
     s = _rates()

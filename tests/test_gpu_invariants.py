@@ -136,6 +136,41 @@ def test_several_steps_per_launch_equal_single_steps(storage, nx, ny):
         assert torch.equal(lat.populations(), ref), (variant, rows, flags)
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("nx,ny", [(1, 1), (5, 3), (63, 9), (130, 70), (200, 5), (3, 130), (260, 33), (520, 40)])
+def test_shared_halo_shapes_equal_single_steps(storage, nx, ny):
+    # workgroup-shared halo (flag 32): the waves of a workgroup exchange
+    # their edge columns through LDS; 1 to 4 waves, T = 4 .. 7, loads one,
+    # two or no rows ahead; lattices narrower than one wave, wider than a
+    # workgroup's strip, ragged and tiny
+    rho, ux, uy = fields(nx, ny, 7, (0.02, -0.01))
+    s = ll_rates()
+    kw = dict(u0=(0.02, -0.01), scale_exp=22 if storage in ("f16", "bf16") else None)
+    ref = lattice(nx, ny, s, storage, **kw).init(rho, ux, uy).step(15).populations()
+    for variant, block_y, rows, flags in [(13, 4, 168, 34), (13, 4, 7, 32), (13, 1, 16, 40), (13, 2, 3, 34),
+                                          (12, 3, 64, 34), (12, 4, 1, 40), (11, 2, 9, 32), (11, 4, 100, 34),
+                                          (10, 1, 2, 34), (10, 3, 33, 40)]:
+        lat = lattice(nx, ny, s, storage, **kw)
+        lat.set_launch(variant=variant, block_x=64, block_y=block_y, rows=rows, xcd_remap=1, flags=flags)
+        assert lat.steps_per_launch == variant - 6
+        lat.init(rho, ux, uy).step(15)
+        assert lat.t == 15
+        assert torch.equal(lat.populations(), ref), (variant, block_y, rows, flags)
+
+
+def test_shared_halo_shapes_are_refused_where_unsupported():
+    from paper_1107_4543_amd import _lib
+    s = ll_rates()
+    lat = lattice(64, 64, s, "f64")
+    with pytest.raises(_lib.LbmError):
+        lat.set_launch(variant=13, block_x=64, block_y=4, rows=64, xcd_remap=1, flags=34)
+    lat = lattice(64, 64, s, "f32")
+    for bad in [dict(variant=9, block_y=4, flags=34), dict(variant=13, block_y=5, flags=34),
+                dict(variant=13, block_y=4, flags=36), dict(variant=13, block_y=4, flags=50)]:
+        with pytest.raises(_lib.LbmError):
+            lat.set_launch(block_x=64, rows=64, xcd_remap=1, **bad)
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_left_over_steps_take_one_shorter_pass(storage):
     # with T = 7, n = 7q + r: q passes, then one r-step pass (r >= 2) or one
