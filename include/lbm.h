@@ -225,6 +225,31 @@ LBM_API lbm_status lbm_read_moments(lbm_lattice *lat, double *rho, double *ux, d
  * Syncs.  Returns LBM_E_NONFINITE when out[3] > 0 (out is still filled). */
 LBM_API lbm_status lbm_diagnostics(lbm_lattice *lat, double out[4]);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops): the diagnostics of lbm_diagnostics for a raw state held by
+ * the caller, with no lattice handle and no workspace.
+ *   desc       describes the state's lattice (validated as by lbm_create, so
+ *              lattices beyond the library's size limits are rejected with
+ *              LBM_E_INVAL); for F16/BF16 storage scale_exp must be the
+ *              state's explicit scale (lbm_get_desc of the lattice it came
+ *              from), LBM_SCALE_AUTO is rejected.
+ *   dev_state  device pointer to the raw state in the layout lbm_save_state
+ *              writes: [9][ny][pitch] values of the storage type, pitch = nx
+ *              rounded up to 64 (columns nx..pitch-1 are not read).
+ *   dev_out    device pointer to 4 doubles, filled as out[] of
+ *              lbm_diagnostics.
+ *   stream     hipStream_t of the current device (NULL = null stream).
+ * Enqueued; never waits, allocates nothing (no hipMalloc, no workspace).
+ * The reduction's partial sums live in a library-owned static device array
+ * of 82,432 bytes per GPU (LBM_NOALLOC_SCRATCH_BYTES), held until the
+ * process ends; its need does not grow with the lattice.  Every call on one
+ * GPU shares that array: calls that overlap on one GPU (different streams
+ * without ordering) race and give wrong sums.  Each call rewrites every
+ * partial it reads, so nothing carries over from an earlier call. */
+#define LBM_NOALLOC_SCRATCH_BYTES 82432
+LBM_API lbm_status lbm_diagnostics_noalloc(const lbm_desc *desc, const void *dev_state, double *dev_out,
+                                           void *stream);
+
 /* FP64 Fourier projection of the population deviations onto the lattice mode
  * k = 2 pi (mx / nx, my / ny), the plane-wave amplitudes of the von Neumann
  * analysis (Sec. 4.1, Eq. perturb-w-f):

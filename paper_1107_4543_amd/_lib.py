@@ -77,6 +77,7 @@ SIGNATURES = {
     "lbm_step": (_st, [_vp, ctypes.c_int64]),
     "lbm_read_moments": (_st, [_vp, _vp, _vp, _vp]),
     "lbm_diagnostics": (_st, [_vp, _dp]),
+    "lbm_diagnostics_noalloc": (_st, [ctypes.POINTER(lbm_desc), _vp, _vp, _vp]),
     "lbm_project": (_st, [_vp, ctypes.c_int32, ctypes.c_int32, _vp]),
     "lbm_read_populations": (_st, [_vp, _vp]),
     "lbm_write_populations": (_st, [_vp, _vp]),
@@ -190,6 +191,13 @@ def lbm_diagnostics(h):
     if s not in (LBM_OK, LBM_E_NONFINITE):
         check(s, "lbm_diagnostics")
     return s, [out[k] for k in range(4)]
+
+
+def lbm_diagnostics_noalloc(desc, dev_state, dev_out, stream):
+    """Enqueues the diagnostics of a raw state into dev_out (4 doubles on the
+    device); allocates nothing."""
+    check(load().lbm_diagnostics_noalloc(ctypes.byref(desc), _vp(dev_state), _vp(dev_out), _vp(stream)),
+          "lbm_diagnostics_noalloc")
 
 
 def lbm_project(h, mx, my, dev_out):

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
 OBJDIR = os.path.join(os.path.dirname(HERE), "_build", "lbm")
 SOURCES = ["lbm_multi_f32.hip", "lbm_multi_f64.hip", "lbm_multi_f16.hip", "lbm_multi_bf16.hip", "lbm_kernels.hip",
-           "lbm_api.hip", "lbm_pool.hip", "lbm_source.hip"]
+           "lbm_api.hip", "lbm_pool.hip", "lbm_source.hip", "lbm_noalloc.hip"]
 HEADERS = ["lbm_device.hpp", "lbm_internal.hpp", "lbm_step_common.hpp", os.path.join("..", "..", "include", "lbm.h")]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 

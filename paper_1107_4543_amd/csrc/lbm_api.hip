@@ -258,6 +258,35 @@ lbm_status time_shape(lbm_lattice *L, const lbm_launch &c, int reps, double *us)
 
 void lbm::set_error_text(const char *msg) { g_err = msg; }
 
+// View of a raw state described by desc alone (no handle, no workspace):
+// validation and layout as for lbm_create; scale_exp must be explicit for
+// 16-bit storage (the scale of a saved state is the lattice's, see
+// lbm_get_desc).
+lbm_status lbm::view_of_state(const lbm_desc *desc, View *v)
+{
+    lbm_status st = validate(desc);
+    if (st != LBM_OK) return st;
+    if (desc->scale_exp == LBM_SCALE_AUTO &&
+        (desc->storage == LBM_STORE_F16 || desc->storage == LBM_STORE_BF16))
+        return fail(LBM_E_INVAL, "16-bit storage needs an explicit scale_exp (the lattice's, from lbm_get_desc)");
+    *v = View{};
+    v->nx = desc->nx;
+    v->ny = desc->ny;
+    v->storage = desc->storage;
+    v->compute = desc->compute;
+    size_t sb, bb;
+    layout(desc, &v->pitch, &v->plane, &sb, &bb);
+    v->s_e = desc->s_e;
+    v->s_eps = desc->s_eps;
+    v->s_q = desc->s_q;
+    v->s_nu = desc->s_nu;
+    v->rho0 = desc->rho0;
+    v->j0x = desc->rho0 * desc->u0x;
+    v->j0y = desc->rho0 * desc->u0y;
+    set_scale(*v, desc->scale_exp == LBM_SCALE_AUTO ? 0 : desc->scale_exp);
+    return LBM_OK;
+}
+
 extern "C" {
 
 const char *lbm_status_string(lbm_status s)

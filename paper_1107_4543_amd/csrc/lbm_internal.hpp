@@ -107,6 +107,11 @@ __host__ __device__ inline int64_t member_multi(int64_t rem, int kk, int T)
 // Sets the text returned by lbm_last_error() on the calling thread.
 void set_error_text(const char *msg);
 
+// Fills *v for a raw state of the lattice that desc describes (validated as
+// by lbm_create; 16-bit storage needs an explicit scale_exp).  Sets the
+// error text on failure.
+lbm_status view_of_state(const lbm_desc *desc, View *v);
+
 Relax<float> relax_f32(const View &v);
 Relax<double> relax_f64(const View &v);
 
