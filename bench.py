@@ -239,9 +239,10 @@ def pool_roofline(T, cells, launches, ms, traffic=None, steps=None):
                  "ops_per_update": ALG_OPS_PER_LU, "hbm": hbm}, **common)
 
 
-# Pool shape the pool tuner selected for batch256 on MI355X (seven steps per
-# launch, 32-row strip tasks, 4 waves per workgroup, flags 12).
-DEFAULT_POOL_SHAPE = "256,512,4096,256,7,32,4,12"
+# Pool shape measured fastest for batch256 on MI355X (seven steps per launch,
+# strip tasks of about 64 rows, 4 waves per workgroup, flags 12; the pool's
+# initial shape).
+DEFAULT_POOL_SHAPE = "256,512,4096,256,7,64,4,12"
 POOL_SHAPE_KEYS = ["tile_cells", "block", "grid", "graph_steps", "steps_per_launch", "seg_rows", "waves", "flags"]
 
 

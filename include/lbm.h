@@ -337,7 +337,9 @@ typedef struct lbm_pool lbm_pool;
  *   steps_per_launch  T = 1, 2, 4, 5, 6 or 7; T > 1 adds strip tasks (columns
  *                as for lbm_launch variants 8-13) of seg_rows rows, one wave
  *                each
- *   seg_rows     rows of a strip task, 1 .. 4096
+ *   seg_rows     rows of a strip task, 1 .. 4096: each member's ny rows are
+ *                cut into max(1, round(ny / seg_rows)) segments of nearly
+ *                equal height (they differ by at most one row)
  *   waves        waves per workgroup of the T-step launch, 1 .. 4
  *   flags        T-step kernel flags as in lbm_launch: 0, 2, 4 or 12
  * The tile table holds the one-step tiles and, for T > 1, the strip tasks
@@ -359,7 +361,7 @@ LBM_API size_t lbm_pool_workspace_bytes(int32_t max_members, int32_t max_tiles);
 /* Creates a pool.  dev_ws: device pointer, 256-byte aligned, at least
  * lbm_pool_workspace_bytes bytes, owned by the caller; stream: the pool's
  * hipStream_t.  Allocates pinned host staging for the tables.  Initial
- * shape {256, 512, 4096, 256, 7, 32, 4, 12} (seven steps per launch). */
+ * shape {256, 512, 4096, 256, 7, 64, 4, 12} (seven steps per launch). */
 LBM_API lbm_status lbm_pool_create(void *dev_ws, size_t ws_bytes, void *stream, int32_t max_members,
                                    int32_t max_tiles, lbm_pool **out);
 /* Returns every member to its lattice (as lbm_pool_remove) and frees the

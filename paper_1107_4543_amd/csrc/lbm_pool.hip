@@ -76,7 +76,7 @@ struct lbm_pool {
     int ntiles = 0;
     int max_class_tiles = 0;         // largest one-step tile range of one class
     int max_class_tasks = 0;         // largest T-step task range of one class
-    lbm_pool_shape shape{256, 512, 4096, 256, 7, 32, 4, 12};
+    lbm_pool_shape shape{256, 512, 4096, 256, 7, 64, 4, 12};
     std::vector<Slot> slots;
     std::vector<int> finishing;      // slot indices in completion order
     std::map<std::tuple<unsigned, int, int, int, int, int>, GraphEntry> graphs;   // (class mask, steps, steps per T-step launch, one-step launches, grids)
@@ -105,11 +105,19 @@ int strip_cols(const lbm_pool_shape &sh, const lbm_lattice *L)
     return lbm::multi_strip_cols(sh.steps_per_launch, bytes[L->v.storage]);
 }
 
+// Segments of a member's strips: the ny rows cut into k = max(1, round(ny
+// / seg_rows)) nearly equal segments (heights differ by at most one row), so
+// that no member ends in a short segment that pays a whole pipeline start-up.
+int segments_of(const lbm_pool_shape &sh, const lbm_lattice *L)
+{
+    return std::max(1, (L->v.ny + sh.seg_rows / 2) / sh.seg_rows);
+}
+
 int tasks_of(const lbm_pool_shape &sh, const lbm_lattice *L)
 {
     if (sh.steps_per_launch < 2) return 0;
     const int w = strip_cols(sh, L);
-    return ((L->v.nx + w - 1) / w) * ((L->v.ny + sh.seg_rows - 1) / sh.seg_rows);
+    return ((L->v.nx + w - 1) / w) * segments_of(sh, L);
 }
 
 // Table entries of one unfinished member: one-step tiles plus T-step tasks.
@@ -182,25 +190,30 @@ lbm_status upload(lbm_pool *P)
                 all.push_back(t);
             }
         if (P->shape.steps_per_launch > 1) {
-            const int w = strip_cols(P->shape, L), sr = P->shape.seg_rows;
-            for (int y0 = 0; y0 < L->v.ny; y0 += sr)
+            const int w = strip_cols(P->shape, L), k = segments_of(P->shape, L);
+            for (int sg = 0; sg < k; ++sg) {
+                const int y0 = (int)((int64_t)L->v.ny * sg / k), y1 = (int)((int64_t)L->v.ny * (sg + 1) / k);
                 for (int x0 = 0; x0 < L->v.nx; x0 += w) {
                     T t{};
                     t.cls = m.cls;
                     t.t.member = i;
                     t.t.y0 = y0;
                     t.t.x0 = x0;
-                    t.t.nrows = std::min(sr, L->v.ny - y0);
+                    t.t.nrows = y1 - y0;
                     t.t.ncols = std::min(w, L->v.nx - x0);
-                    t.cells = (int64_t)t.t.nrows * t.t.ncols;
+                    // a wave's time follows its rows (every lane works, a
+                    // partial strip or not)
+                    t.cells = (int64_t)t.t.nrows * 64;
                     tasks.push_back(t);
                 }
+            }
         }
     }
     if ((int)(all.size() + tasks.size()) > P->max_tiles)
         return pfail(LBM_E_NOMEM, "pool needs %zu tiles, has %d", all.size() + tasks.size(), P->max_tiles);
-    // group by class, largest first (balances the strided persistent grid);
-    // one-step tiles, then T-step tasks
+    // group by class, longest first (the hardware starts workgroups in
+    // order, so the short tasks fill the end of the launch); one-step tiles,
+    // then T-step tasks
     auto order = [](const T &a, const T &b) { return a.cls != b.cls ? a.cls < b.cls : a.cells > b.cells; };
     std::stable_sort(all.begin(), all.end(), order);
     std::stable_sort(tasks.begin(), tasks.end(), order);
@@ -716,7 +729,7 @@ lbm_status lbm_pool_tune(lbm_pool *pool, int32_t reps, lbm_pool_shape *best, dou
             }
     // several steps per launch (their left-over steps use the best one-step tiles)
     for (int T : {2, 4, 5, 6, 7})
-        for (int seg : {32, 64, 128})
+        for (int seg : {32, 48, 64, 80, 128})
             for (int waves : {1, 4})
                 for (int flags : {0, 2, 12})
                     for (int grid : {4096, 16384, 65536}) {
