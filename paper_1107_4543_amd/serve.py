@@ -5,9 +5,10 @@ a number of steps.  ``Server.run`` replays a trace of jobs in real time:
 
 * jobs whose arrival time has passed wait in a queue, ordered by the
   admission policy: shortest job first with ageing ("aged", the default:
-  least cells x steps first, but a job that has waited a fixed time plus
-  half its estimated service time goes ahead of all younger jobs, so no job
-  starves), plain shortest job first ("sjf") or arrival order ("fifo");
+  least cells x steps first, but a job that has waited a fixed second plus
+  four times its estimated service time goes ahead of all younger jobs, so
+  no job starves), plain shortest job first ("sjf") or arrival order
+  ("fifo");
 * the head of the queue is admitted as soon as its device footprint fits in
   the HBM budget, the pool has a free member slot and the cells being
   advanced stay under a cap: its workspace is allocated, its fields are
@@ -156,9 +157,10 @@ def percentile(xs, q):
 # estimated service time
 SERVICE_LUPS_ESTIMATE = 2.5e11
 # a queued job is "aged" once it has waited AGE_FIXED_S + AGE_FACTOR times its
-# estimated service time
-AGE_FIXED_S = 0.05
-AGE_FACTOR = 0.5
+# estimated service time: late enough that a lightly loaded server never
+# reorders (it then admits shortest first), soon enough to bound every wait
+AGE_FIXED_S = 1.0
+AGE_FACTOR = 4.0
 
 
 def service_estimate(spec):

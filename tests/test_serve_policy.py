@@ -5,7 +5,7 @@ that does not fit blocks the jobs behind it.  Under a sustained stream of
 small jobs that keeps the cell cap nearly full, shortest-job-first keeps
 putting new small jobs ahead of a large one, so the large job waits until
 the stream ends; with ageing ("aged", the server's default) a job that has
-waited a fixed time plus half its estimated service time goes first, so the
+waited a fixed time plus a multiple of its estimated service time goes first, so the
 large job reaches the head, blocks the stream until enough cells drain, and
 is admitted after a bounded wait that does not depend on how long the
 stream lasts.
@@ -79,10 +79,14 @@ def test_order_queue_policies():
     assert serve.service_estimate(a) == pytest.approx(4.0)
     assert [j.tag for j in serve.order_queue([c, b, a], "fifo", 1.5)] == [1, 2, 3]
     assert [j.tag for j in serve.order_queue([a, c, b], "sjf", 1.5)] == [2, 3, 1]
-    # at t = 1.5 only the small jobs have waited long enough to age, and
-    # aged jobs go in arrival order ahead of the large one
-    assert not serve.is_aged(a, 1.5) and serve.is_aged(b, 1.5) and not serve.is_aged(c, 1.5)
+    # nobody aged yet: shortest first
+    assert not any(serve.is_aged(j, 1.5) for j in (a, b, c))
     assert [j.tag for j in serve.order_queue([a, c, b], "aged", 1.5)] == [2, 3, 1]
+    # small jobs age after AGE_FIXED_S (their service is negligible), and
+    # aged jobs go in arrival order ahead of younger ones
+    t_small = 1.5 + serve.AGE_FIXED_S + 1e-6
+    assert serve.is_aged(b, t_small) and serve.is_aged(c, t_small) and not serve.is_aged(a, t_small)
+    assert [j.tag for j in serve.order_queue([a, c, b], "aged", t_small)] == [2, 3, 1]
     # once the large job has waited AGE_FIXED_S + AGE_FACTOR x 4 s it goes first
     t_old = serve.AGE_FIXED_S + serve.AGE_FACTOR * 4.0 + 1e-6
     assert serve.is_aged(a, t_old)
@@ -94,7 +98,7 @@ def test_order_queue_policies():
 
 def test_sjf_starves_the_large_job_and_ageing_bounds_its_wait():
     serve = _serve_module()
-    burst = 20.0
+    burst = 40.0
     jobs, cap, lups = stream_with_large_job(burst)
     sjf = simulate("sjf", jobs, cap, lups)
     aged = simulate("aged", jobs, cap, lups)
@@ -108,13 +112,13 @@ def test_sjf_starves_the_large_job_and_ageing_bounds_its_wait():
     assert wait["aged"] <= bound, wait
     # every small job is still served, each within a bounded wait
     small_waits = [aged[j.tag] - j.arrival for j in jobs if j.tag >= 0]
-    assert len(small_waits) == len(jobs) - 1 and max(small_waits) <= 10.0
+    assert len(small_waits) == len(jobs) - 1 and max(small_waits) <= 20.0
     assert wait["fifo"] <= 0.01                # arrival order admits it at once here
 
 
 def test_aged_wait_bound_does_not_grow_with_the_burst():
-    jobs10, cap, lups = stream_with_large_job(10.0)
-    jobs40, _, _ = stream_with_large_job(40.0)
-    w10 = simulate("aged", jobs10, cap, lups)[-1] - 0.5
-    w40 = simulate("aged", jobs40, cap, lups)[-1] - 0.5
-    assert abs(w40 - w10) <= 0.01
+    jobs30, cap, lups = stream_with_large_job(30.0)
+    jobs60, _, _ = stream_with_large_job(60.0)
+    w30 = simulate("aged", jobs30, cap, lups)[-1] - 0.5
+    w60 = simulate("aged", jobs60, cap, lups)[-1] - 0.5
+    assert abs(w60 - w30) <= 0.01
