@@ -103,10 +103,11 @@ typedef struct lbm_lattice lbm_lattice;
 /* Launch shape of the fused step kernel (chosen by lbm_tune or set by hand;
  * a new lattice of at least 2^22 cells starts with a several-steps shape
  * by storage type: FP32 {13, 64, 4, R, 1, 32}, FP16 {12, 64, 4, R, 1, 34},
- * BF16 {11, 64, 4, R, 1, 40} (workgroup-shared halo, R chosen from the
- * lattice size so that three (FP32) or four (FP16, BF16) workgroups per
- * compute unit cover the lattice in one round: 92, 69, 69 rows on 4096^2),
- * FP64 {13, 64, 4, 168, 1, 12}; a smaller one with {0, 64, 4, 1, 1, 0}).
+ * BF16 {11, 64, 4, R, 1, 40}, FP64 {13, 64, 4, R, 1, 32} (workgroup-shared
+ * halo, R chosen from the lattice size so that three (FP32), four (FP16,
+ * BF16) or two (FP64) workgroups per compute unit cover the lattice in one
+ * round: 92, 69, 69, 137 rows on 4096^2); a smaller one with
+ * {0, 64, 4, 1, 1, 0}).
  *   variant   0 = one cell per lane (nine direct loads),
  *             1, 2, 3 = 2, 4, 8 consecutive cells per lane (aligned vector
  *             loads, x-shift by cross-lane exchange; needs nx % 2^variant == 0
@@ -141,13 +142,15 @@ typedef struct lbm_lattice lbm_lattice;
  *             skewed pipeline, in which stage p works two rows behind stage
  *             p-1 instead of one, so that the T collisions of a row
  *             iteration do not depend on each other; bit 5 (variants
- *             10-13, FP32/FP16/BF16 storage, flags 32, 34 or 40 only):
+ *             10-13 with flags 32, 34, 40, or with bit 4 set, 48, 50, 56;
+ *             FP64 storage: variants 12-13, flags 32, 34, 40):
  *             workgroup-shared halo -- the block_y waves of a workgroup
  *             own one strip of 64 block_y - 2(T-1) columns (rounded as
  *             above) and pass the values a stage takes from the
  *             neighbouring column through LDS (with a workgroup barrier per
- *             stage), so that only the workgroup's outer edges recompute a
- *             halo.
+ *             stage; with bit 4, one per row through two alternating
+ *             buffers), so that only the workgroup's outer edges recompute
+ *             a halo.
  * Every shape produces bit-identical results. */
 typedef struct lbm_launch {
     int32_t variant;

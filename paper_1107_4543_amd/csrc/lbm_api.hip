@@ -134,10 +134,10 @@ int wg_rows(const View &v, int T, int waves, int per_cu)
 // workgroup -- FP32: T = 7, loads not ahead (flags 32), segments for three
 // workgroups per compute unit (92 rows on 4096^2); FP16: T = 6, loads one row
 // ahead (34), four per compute unit (69 rows); BF16: T = 5, two rows ahead
-// (40), four per compute unit (69 rows) -- and for FP64 storage T = 7 with
-// one wave per strip (13, 4, 168, 12).  Smaller lattices offer too few
-// strip segments to keep the GPU busy through the pipeline and keep the
-// one-step shape.
+// (40), four per compute unit (69 rows); FP64: T = 7, loads not ahead (32),
+// two per compute unit (137 rows; a wave then holds about 250 registers).
+// Smaller lattices offer too few strip segments to keep the GPU busy through
+// the pipeline and keep the one-step shape.
 lbm_launch default_launch(const View &v)
 {
     if ((int64_t)v.nx * v.ny < ((int64_t)1 << 22)) return default_single(v);
@@ -148,7 +148,7 @@ lbm_launch default_launch(const View &v)
     case LBM_STORE_F32: c.variant = 13; c.block_y = 4; c.flags = 32; c.rows = wg_rows(v, 7, 4, 3); break;
     case LBM_STORE_F16: c.variant = 12; c.block_y = 4; c.flags = 34; c.rows = wg_rows(v, 6, 4, 4); break;
     case LBM_STORE_BF16: c.variant = 11; c.block_y = 4; c.flags = 40; c.rows = wg_rows(v, 5, 4, 4); break;
-    default: c.variant = 13; c.block_y = 4; c.rows = 168; c.flags = 12; break;
+    default: c.variant = 13; c.block_y = 4; c.flags = 32; c.rows = wg_rows(v, 7, 4, 2); break;
     }
     return c;
 }
@@ -198,8 +198,8 @@ std::vector<lbm_launch> multi_candidates(const View &v)
 {
     std::vector<lbm_launch> out;
     for (int var = 10; var <= 13; ++var)
-        for (int flags : {32, 34, 40})
-            for (int per_cu : {2, 3, 4}) {
+        for (int flags : {32, 34, 40, 48, 50})
+            for (int per_cu : {1, 2, 3, 4}) {
                 lbm_launch c{};
                 c.variant = var;
                 c.block_x = 64;

@@ -825,13 +825,17 @@ bool step_shape_supported(const View &v, const lbm_launch &cfg)
     if (cfg.variant >= 8 && cfg.variant <= 13) {
         // several steps per pass: one wave per strip and segment
         if (cfg.variant >= 11 && (cfg.flags & 1)) return false;   // T = 5, 6, 7: no non-temporal loads
-        if (cfg.variant == 13 && (cfg.flags & 16)) return false;  // T = 7: plain pipeline only
+        // T = 7 with one wave per strip: plain pipeline only
+        if (cfg.variant == 13 && (cfg.flags & 16) && !(cfg.flags & kWgHalo)) return false;
         if (cfg.flags & kWgHalo) {
-            // shared halo: T = 4 .. 7, flags 32, 34 or 40 (plain pipeline,
-            // no shuffles, loads one or two rows ahead or none), 32- or
-            // 16-bit wide values (FP32 arithmetic on the stored type)
-            if (cfg.variant < 10 || v.storage == LBM_STORE_F64) return false;
-            if (cfg.flags != kWgHalo && cfg.flags != (kWgHalo | 2) && cfg.flags != (kWgHalo | 8)) return false;
+            // shared halo: T = 4 .. 7, flags 32, 34 or 40 (no shuffles,
+            // loads one or two rows ahead or none), plain or skewed
+            // pipeline (+16); FP64 storage only T = 6, 7, plain
+            if (cfg.variant < 10) return false;
+            const int f = cfg.flags & ~16;      // bit 4: the skewed pipeline, one exchange per row
+            if (f != kWgHalo && f != (kWgHalo | 2) && f != (kWgHalo | 8)) return false;
+            // FP64 storage: T = 6 and 7, plain pipeline
+            if (v.storage == LBM_STORE_F64 && (cfg.variant < 12 || (cfg.flags & 16))) return false;
             return cfg.block_x == 64 && cfg.block_y >= 1 && cfg.block_y <= kWgMaxWaves && cfg.rows >= 1 &&
                    cfg.rows <= 4096 && (cfg.xcd_remap == 0 || cfg.xcd_remap == 1);
         }

@@ -30,7 +30,8 @@ hipError_t launch_multi_impl(const StepArgs<C> &a, dim3 grid, dim3 block, int T,
         // T = 7: plain pipeline only
         LBM_MULTI(7, 0) LBM_MULTI(7, 2) LBM_MULTI(7, 4) LBM_MULTI(7, 6) LBM_MULTI(7, 8) LBM_MULTI(7, 12)
         // workgroup-shared halo (bit 5), T = 4 .. 7
-#define LBM_MULTI_WG(T_) LBM_MULTI(T_, 32) LBM_MULTI(T_, 34) LBM_MULTI(T_, 40)
+#define LBM_MULTI_WG(T_) LBM_MULTI(T_, 32) LBM_MULTI(T_, 34) LBM_MULTI(T_, 40) \
+                         LBM_MULTI(T_, 48) LBM_MULTI(T_, 50) LBM_MULTI(T_, 56)
         LBM_MULTI_WG(4)
         LBM_MULTI_WG(5)
         LBM_MULTI_WG(6)

@@ -29,6 +29,8 @@ hipError_t launch_multi_impl(const StepArgs<C> &a, dim3 grid, dim3 block, int T,
         LBM_MULTI_E(6)
         // T = 7: plain pipeline only
         LBM_MULTI(7, 0) LBM_MULTI(7, 2) LBM_MULTI(7, 4) LBM_MULTI(7, 6) LBM_MULTI(7, 8) LBM_MULTI(7, 12)
+        // workgroup-shared halo (bit 5), T = 6 and 7, plain pipeline
+        LBM_MULTI(6, 32) LBM_MULTI(6, 34) LBM_MULTI(6, 40) LBM_MULTI(7, 32) LBM_MULTI(7, 34) LBM_MULTI(7, 40)
 #undef LBM_MULTI_E
 #undef LBM_MULTI_T
 #undef LBM_MULTI

@@ -340,19 +340,22 @@ __device__ __forceinline__ bool one_resource(int64_t plane)
 // columns x0 - (T-1) + 64 threadIdx.y + lane; cols <= 64 blockDim.y -
 // 2(T-1)), and every wave of the workgroup must call with the same
 // arguments.
-// LDS of the shared-halo exchange: stage boundary b (output of stage b),
-// value k (populations 1, 3, 5, 6, 7, 8), column of the workgroup's lanes.
+// LDS of the shared-halo exchange: [buffer][stage boundary b (output of
+// stage b)][value k (populations 1, 3, 5, 6, 7, 8)][column of the
+// workgroup's lanes]; one buffer for the plain pipeline, two (alternating
+// rows) for the skewed one.
 constexpr int kWgXchCols = 64 * kWgMaxWaves;
-template <typename S, int T>
-struct WgExchange {
-    typename Store<S>::wide v[(T - 1) * 6 * kWgXchCols];
-};
+template <int T, int FLAGS>
+constexpr int wg_exchange_values()
+{
+    return (FLAGS & kWgHalo) ? (T - 1) * 6 * kWgXchCols * ((FLAGS & 16) ? 2 : 1) : 1;
+}
 
 template <typename S, typename C, int T, int FLAGS, bool ONE_RSRC>
 __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *__restrict__ dst, int nx, int ny,
                                            int pitch, int64_t plane, const Relax<C> &relax, float scale,
                                            float inv_scale, int x0, int cols, int y0, int len,
-                                           WgExchange<S, T> *wgx = nullptr)
+                                           typename Store<S>::wide *wgx = nullptr)
 {
     using R = typename Store<S>::raw;
     using W = typename Store<S>::wide;
@@ -365,7 +368,6 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
     // earlier iterations, so the T collides of an iteration are independent
     constexpr bool SKEW = (FLAGS & 16) != 0;
     constexpr int LAG = SKEW ? 3 : 2;                   // iterations from one stage's start to the next
-    static_assert(!(WG && SKEW), "the workgroup-shared halo runs the plain pipeline");
     constexpr uint32_t E = sizeof(R);
     const int lane = threadIdx.x;
     // column of this lane within the strip's lanes (the workgroup's with the
@@ -381,7 +383,7 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
     // columns are clamped at the workgroup's edges (those lanes' results are
     // not used)
     constexpr int XW = kWgXchCols;
-    W *const xch = WG ? wgx->v : nullptr;
+    W *const xch = WG ? wgx : nullptr;
     const int lanes = WG ? 64 * (int)blockDim.y : 64;
     const int lcl = lc > 0 ? lc - 1 : 0, lcr = lc + 1 < lanes ? lc + 1 : lc;
     const uint64_t pb = (uint64_t)plane * E;
@@ -563,15 +565,28 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
             const bool active = STEADY || j >= 3 * p;   // wave-uniform
             W in[9];
             if (active) {
-                in[0] = r2[p - 1][0];
-                in[1] = from_left<DPP>(r2[p - 1][1]);
-                in[3] = from_right<DPP>(r2[p - 1][2]);
-                in[2] = r3[p - 1][0];
-                in[5] = from_left<DPP>(r3[p - 1][1]);
-                in[6] = from_right<DPP>(r3[p - 1][2]);
-                in[4] = r1[p - 1][4];
-                in[7] = from_right<DPP>(r1[p - 1][7]);
-                in[8] = from_left<DPP>(r1[p - 1][8]);
+                if constexpr (WG) {
+                    // shifted by the exchange at the end of the row that produced them
+                    in[0] = r2[p - 1][0];
+                    in[1] = r2[p - 1][1];
+                    in[3] = r2[p - 1][2];
+                    in[2] = r3[p - 1][0];
+                    in[5] = r3[p - 1][1];
+                    in[6] = r3[p - 1][2];
+                    in[4] = r1[p - 1][4];
+                    in[7] = r1[p - 1][7];
+                    in[8] = r1[p - 1][8];
+                } else {
+                    in[0] = r2[p - 1][0];
+                    in[1] = from_left<DPP>(r2[p - 1][1]);
+                    in[3] = from_right<DPP>(r2[p - 1][2]);
+                    in[2] = r3[p - 1][0];
+                    in[5] = from_left<DPP>(r3[p - 1][1]);
+                    in[6] = from_right<DPP>(r3[p - 1][2]);
+                    in[4] = r1[p - 1][4];
+                    in[7] = from_right<DPP>(r1[p - 1][7]);
+                    in[8] = from_left<DPP>(r1[p - 1][8]);
+                }
                 cell_update<S, C>(in, relax, scale, inv_scale);
                 if (p == T - 1 && writes) store_row((uint32_t)(r - 2 * (T - 1)) * rb, in);
             } else {
@@ -594,6 +609,34 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
             r2[p - 1][5] = r1[p - 1][6];
 #pragma unroll
             for (int i = 0; i < 9; ++i) r1[p - 1][i] = round_trip<S>(p == 1 ? w[i] : res[p - 2][i]);
+        }
+        if constexpr (WG) {
+            // One exchange per row: every stage's new output goes through this
+            // row's buffer (rows alternate between two, so a barrier of the
+            // next row separates these reads from the writes that reuse it)
+            // and comes back shifted to the neighbouring columns.
+            W *const xb0 = xch + (j & 1) * (T - 1) * 6 * XW;
+#pragma unroll
+            for (int b = 0; b < T - 1; ++b) {
+                W *xb = xb0 + b * 6 * XW;
+                xb[0 * XW + lc] = r1[b][1];
+                xb[1 * XW + lc] = r1[b][3];
+                xb[2 * XW + lc] = r1[b][5];
+                xb[3 * XW + lc] = r1[b][6];
+                xb[4 * XW + lc] = r1[b][7];
+                xb[5 * XW + lc] = r1[b][8];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int b = 0; b < T - 1; ++b) {
+                const W *xb = xb0 + b * 6 * XW;
+                r1[b][1] = xb[0 * XW + lcl];
+                r1[b][3] = xb[1 * XW + lcr];
+                r1[b][5] = xb[2 * XW + lcl];
+                r1[b][6] = xb[3 * XW + lcr];
+                r1[b][7] = xb[4 * XW + lcr];
+                r1[b][8] = xb[5 * XW + lcl];
+            }
         }
     };
     // Two rows per trip (the compiler does not unroll loops that hold
@@ -626,13 +669,18 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
 }
 
 // Waves per SIMD the register allocation of a several-steps kernel aims
-// for: with the shared halo (36 KB of LDS per workgroup at T = 7) four
-// workgroups of four waves fit a CU when a wave takes at most 128 VGPRs.
-template <int FLAGS>
-constexpr int multi_waves_per_eu() { return (FLAGS & kWgHalo) ? 4 : 1; }
+// for: with the shared halo (36 KB of LDS per workgroup at T = 7 for 32-bit
+// values) four workgroups of four waves fit a CU when a wave takes at most
+// 128 VGPRs (the skewed pipeline holds more rows: two); FP64 values need
+// twice the registers and LDS (one).
+template <typename S, int FLAGS>
+constexpr int multi_waves_per_eu()
+{
+    return !(FLAGS & kWgHalo) || sizeof(typename Store<S>::wide) == 8 ? 1 : ((FLAGS & 16) ? 2 : 4);
+}
 
 template <typename S, typename C, int T, int FLAGS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(multi_waves_per_eu<FLAGS>())))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(multi_waves_per_eu<S, FLAGS>())))
 k_step_multi(StepArgs<C> a)
 {
     const int OUT = a.out_cols;
@@ -645,20 +693,20 @@ k_step_multi(StepArgs<C> a)
     if (wave >= a.nwaves) return;                       // whole waves (workgroups) only
     const int strip = wave % a.tiles_x, seg = wave / a.tiles_x;
     const int y0 = seg * a.tile_h;
-    __shared__ WgExchange<S, (FLAGS & kWgHalo) ? T : 2> wgx;
+    __shared__ typename Store<S>::wide wgx[wg_exchange_values<T, FLAGS>()];
     // one resource per buffer where it measured faster (FP32 storage: +2 %;
     // with 16-bit storage and in the pool it was slower), else per plane row
     if constexpr (std::is_same<S, float>::value) {
         if (one_resource<S>(a.plane)) {
             strip_pass<S, C, T, FLAGS, true>((const char *)a.src, (char *)a.dst, a.nx, a.ny, a.pitch, a.plane, a.r,
                                              a.scale, a.inv_scale, strip * OUT, OUT, y0, min(a.tile_h, a.ny - y0),
-                                             (WgExchange<S, T> *)&wgx);
+                                             wgx);
             return;
         }
     }
     strip_pass<S, C, T, FLAGS, false>((const char *)a.src, (char *)a.dst, a.nx, a.ny, a.pitch, a.plane, a.r,
                                       a.scale, a.inv_scale, strip * OUT, OUT, y0, min(a.tile_h, a.ny - y0),
-                                      (WgExchange<S, T> *)&wgx);
+                                      wgx);
 }
 
 template <typename C>

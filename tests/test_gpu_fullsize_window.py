@@ -12,8 +12,9 @@ block of the full run exactly (pinned on the CPU by
 test_window_run_reproduces_the_centre_of_a_larger_periodic_run).  The blocks
 straddle the places where the kernel's work is cut: strip edges, segment
 edges and the lattice's periodic wrap.
-Tolerances: FP32 within 1e-5 A on the density and 1e-5 A_u on the velocity;
-FP16 and BF16 storage within the rounding bound 3 u sqrt(T) A.
+Tolerances: FP64 to 1e-12 of the density (and the velocity, momentum-relative);
+FP32 within 1e-5 A on the density and 1e-5 A_u on the velocity; FP16 and BF16
+storage within the rounding bound 3 u sqrt(T) A.
 """
 import numpy as np
 import pytest
@@ -65,7 +66,7 @@ def workload():
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
 def test_benched_shape_matches_window_oracle(workload, storage):
     from paper_1107_4543_amd import Lattice
     specs, u0x, s, blocks = workload
@@ -89,7 +90,12 @@ def test_benched_shape_matches_window_oracle(workload, storage):
         gr = r[yi][:, xi].cpu().numpy()
         e = float(np.max(np.abs(gr - rb))) / A
         worst = max(worst, e)
-        if unit is None:
+        if storage == "f64":
+            eu = max(float(np.max(np.abs(u[yi][:, xi].cpu().numpy() - ub))),
+                     float(np.max(np.abs(w[yi][:, xi].cpu().numpy() - wb))))
+            assert float(np.max(np.abs(gr - rb))) <= 1e-12 * float(np.max(np.abs(rb))), (storage, ys[0], xs[0])
+            assert eu <= 1e-12 * float(np.max(np.abs(rb))), (storage, ys[0], xs[0])
+        elif unit is None:
             Au = lbm_inputs.CS * A
             eu = max(float(np.max(np.abs(u[yi][:, xi].cpu().numpy() - ub))),
                      float(np.max(np.abs(w[yi][:, xi].cpu().numpy() - wb))))

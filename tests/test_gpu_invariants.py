@@ -141,15 +141,19 @@ def test_several_steps_per_launch_equal_single_steps(storage, nx, ny):
 def test_shared_halo_shapes_equal_single_steps(storage, nx, ny):
     # workgroup-shared halo (flag 32): the waves of a workgroup exchange
     # their edge columns through LDS; 1 to 4 waves, T = 4 .. 7, loads one,
-    # two or no rows ahead; lattices narrower than one wave, wider than a
-    # workgroup's strip, ragged and tiny
+    # two or no rows ahead, plain or skewed pipeline (one exchange per
+    # stage, or one per row through two alternating buffers); lattices
+    # narrower than one wave, wider than a workgroup's strip, ragged and tiny
     rho, ux, uy = fields(nx, ny, 7, (0.02, -0.01))
     s = ll_rates()
     kw = dict(u0=(0.02, -0.01), scale_exp=22 if storage in ("f16", "bf16") else None)
     ref = lattice(nx, ny, s, storage, **kw).init(rho, ux, uy).step(15).populations()
     for variant, block_y, rows, flags in [(13, 4, 168, 34), (13, 4, 7, 32), (13, 1, 16, 40), (13, 2, 3, 34),
                                           (12, 3, 64, 34), (12, 4, 1, 40), (11, 2, 9, 32), (11, 4, 100, 34),
-                                          (10, 1, 2, 34), (10, 3, 33, 40)]:
+                                          (10, 1, 2, 34), (10, 3, 33, 40),
+                                          # skewed pipeline, one exchange per row (flags 48, 50, 56)
+                                          (13, 4, 137, 48), (13, 4, 5, 50), (13, 2, 17, 56), (12, 4, 64, 48),
+                                          (12, 1, 3, 50), (11, 3, 41, 56), (10, 4, 1, 48), (10, 2, 200, 50)]:
         lat = lattice(nx, ny, s, storage, **kw)
         lat.set_launch(variant=variant, block_x=64, block_y=block_y, rows=rows, xcd_remap=1, flags=flags)
         assert lat.steps_per_launch == variant - 6
@@ -158,15 +162,31 @@ def test_shared_halo_shapes_equal_single_steps(storage, nx, ny):
         assert torch.equal(lat.populations(), ref), (variant, block_y, rows, flags)
 
 
+@pytest.mark.parametrize("compute", ["f64", "f32"])
+@pytest.mark.parametrize("nx,ny", [(1, 1), (63, 9), (130, 70), (520, 40)])
+def test_shared_halo_shapes_equal_single_steps_fp64_storage(compute, nx, ny):
+    rho, ux, uy = fields(nx, ny, 8, (0.02, -0.01))
+    s = ll_rates()
+    kw = dict(u0=(0.02, -0.01), compute=compute)
+    ref = lattice(nx, ny, s, "f64", **kw).init(rho, ux, uy).step(15).populations()
+    for variant, block_y, rows, flags in [(13, 4, 137, 32), (13, 2, 9, 34), (12, 4, 64, 40), (12, 3, 1, 32)]:
+        lat = lattice(nx, ny, s, "f64", **kw)
+        lat.set_launch(variant=variant, block_x=64, block_y=block_y, rows=rows, xcd_remap=1, flags=flags)
+        lat.init(rho, ux, uy).step(15)
+        assert torch.equal(lat.populations(), ref), (variant, block_y, rows, flags)
+
+
 def test_shared_halo_shapes_are_refused_where_unsupported():
     from paper_1107_4543_amd import _lib
     s = ll_rates()
     lat = lattice(64, 64, s, "f64")
-    with pytest.raises(_lib.LbmError):
-        lat.set_launch(variant=13, block_x=64, block_y=4, rows=64, xcd_remap=1, flags=34)
+    for bad in [dict(variant=11, flags=34), dict(variant=13, flags=48)]:
+        with pytest.raises(_lib.LbmError):
+            lat.set_launch(block_x=64, block_y=4, rows=64, xcd_remap=1, **bad)
     lat = lattice(64, 64, s, "f32")
     for bad in [dict(variant=9, block_y=4, flags=34), dict(variant=13, block_y=5, flags=34),
-                dict(variant=13, block_y=4, flags=36), dict(variant=13, block_y=4, flags=50)]:
+                dict(variant=13, block_y=4, flags=36), dict(variant=13, block_y=4, flags=52),
+                dict(variant=9, block_y=4, flags=48)]:
         with pytest.raises(_lib.LbmError):
             lat.set_launch(block_x=64, rows=64, xcd_remap=1, **bad)
 
