@@ -304,6 +304,39 @@ __device__ __forceinline__ typename Store<S>::wide round_trip(typename Store<S>:
     return Store<S>::widen(Store<S>::narrow(v));
 }
 
+// round_trip of a cell's nine values.  16-bit storage converts two values
+// per instruction (v_cvt_pk_f16_f32 / v_cvt_pk_bf16_f32, round to nearest
+// even like the scalar conversions of Store<>::narrow, so the results are the
+// same bits) and widens the halves back; other types as round_trip.
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+template <typename S>
+__device__ __forceinline__ void round_trip9(typename Store<S>::wide w[9])
+{
+    if constexpr (std::is_same<S, f16_tag>::value) {
+#pragma unroll
+        for (int i = 0; i < 8; i += 2) {
+            const f16x2_t h = __builtin_convertvector((f32x2_t){w[i], w[i + 1]}, f16x2_t);
+            w[i] = (float)h.x;
+            w[i + 1] = (float)h.y;
+        }
+        w[8] = round_trip<S>(w[8]);
+    } else if constexpr (std::is_same<S, bf16_tag>::value) {
+#pragma unroll
+        for (int i = 0; i < 8; i += 2) {
+            const uint32_t u = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){w[i], w[i + 1]}, bf16x2_t));
+            w[i] = __uint_as_float(u << 16);
+            w[i + 1] = __uint_as_float(u & 0xffff0000u);
+        }
+        w[8] = round_trip<S>(w[8]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) w[i] = round_trip<S>(w[i]);
+    }
+}
+
 __device__ __forceinline__ int wrap_mod(int v, int n)
 {
     v %= n;
@@ -478,8 +511,7 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
 #pragma unroll
         for (int p = 1; p < T; ++p) {
             // w holds stage p-1's output, row r - p + 1
-#pragma unroll
-            for (int i = 0; i < 9; ++i) w[i] = round_trip<S>(w[i]);
+            round_trip9<S>(w);
             W in[9];
             const bool active = STEADY || j >= 2 * p;   // wave-uniform (workgroup-uniform)
             if constexpr (WG) {
@@ -608,7 +640,8 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
             r2[p - 1][4] = r1[p - 1][5];
             r2[p - 1][5] = r1[p - 1][6];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) r1[p - 1][i] = round_trip<S>(p == 1 ? w[i] : res[p - 2][i]);
+            for (int i = 0; i < 9; ++i) r1[p - 1][i] = p == 1 ? w[i] : res[p - 2][i];
+            round_trip9<S>(r1[p - 1]);
         }
         if constexpr (WG) {
             // One exchange per row: every stage's new output goes through this
