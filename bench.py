@@ -98,7 +98,7 @@ def read_traffic(workload, storage, launch):
 # (variants 11, 12 and 13: five, six and seven steps per pass; flag 32: the
 # workgroup-shared halo); the library's defaults for this lattice; --tune
 # searches again.
-DEFAULT_LAUNCH = {"f32": "13,64,4,92,1,32", "f16": "11,64,4,69,1,40", "bf16": "11,64,4,69,1,40",
+DEFAULT_LAUNCH = {"f32": "13,64,4,92,1,32", "f16": "12,64,4,69,1,34", "bf16": "12,64,4,69,1,40",
                   "f64": "13,64,4,137,1,32"}
 
 

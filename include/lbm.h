@@ -102,8 +102,8 @@ typedef struct lbm_lattice lbm_lattice;
 
 /* Launch shape of the fused step kernel (chosen by lbm_tune or set by hand;
  * a new lattice of at least 2^22 cells starts with a several-steps shape
- * by storage type: FP32 {13, 64, 4, R, 1, 32}, FP16 and BF16
- * {11, 64, 4, R, 1, 40}, FP64 {13, 64, 4, R, 1, 32} (workgroup-shared
+ * by storage type: FP32 {13, 64, 4, R, 1, 32}, FP16 {12, 64, 4, R, 1, 34},
+ * BF16 {12, 64, 4, R, 1, 40}, FP64 {13, 64, 4, R, 1, 32} (workgroup-shared
  * halo, R chosen from the lattice size so that three (FP32), four (FP16,
  * BF16) or two (FP64) workgroups per compute unit cover the lattice in one
  * round: 92, 69, 69, 137 rows on 4096^2); a smaller one with

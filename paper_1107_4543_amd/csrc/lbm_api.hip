@@ -132,8 +132,9 @@ int wg_rows(const View &v, int T, int waves, int per_cu)
 // measured fastest for the storage type on the 4096^2 wave workload: for
 // 32- and 16-bit storage the workgroup-shared halo with four waves per
 // workgroup -- FP32: T = 7, loads not ahead (flags 32), segments for three
-// workgroups per compute unit (92 rows on 4096^2); FP16 and BF16: T = 5, two
-// rows ahead (40), four per compute unit (69 rows); FP64: T = 7, loads not ahead (32),
+// workgroups per compute unit (92 rows on 4096^2); FP16: T = 6, one row
+// ahead (34), BF16: T = 6, two rows ahead (40), four per compute unit (69
+// rows); FP64: T = 7, loads not ahead (32),
 // two per compute unit (137 rows; a wave then holds about 250 registers).
 // Smaller lattices offer too few strip segments to keep the GPU busy through
 // the pipeline and keep the one-step shape.
@@ -145,8 +146,8 @@ lbm_launch default_launch(const View &v)
     c.xcd_remap = 1;
     switch (v.storage) {
     case LBM_STORE_F32: c.variant = 13; c.block_y = 4; c.flags = 32; c.rows = wg_rows(v, 7, 4, 3); break;
-    case LBM_STORE_F16: c.variant = 11; c.block_y = 4; c.flags = 40; c.rows = wg_rows(v, 5, 4, 4); break;
-    case LBM_STORE_BF16: c.variant = 11; c.block_y = 4; c.flags = 40; c.rows = wg_rows(v, 5, 4, 4); break;
+    case LBM_STORE_F16: c.variant = 12; c.block_y = 4; c.flags = 34; c.rows = wg_rows(v, 6, 4, 4); break;
+    case LBM_STORE_BF16: c.variant = 12; c.block_y = 4; c.flags = 40; c.rows = wg_rows(v, 6, 4, 4); break;
     default: c.variant = 13; c.block_y = 4; c.flags = 32; c.rows = wg_rows(v, 7, 4, 2); break;
     }
     return c;
