@@ -344,7 +344,12 @@ typedef struct lbm_pool lbm_pool;
  *                cut into max(1, round(ny / seg_rows)) segments of nearly
  *                equal height (they differ by at most one row)
  *   waves        waves per workgroup of the T-step launch, 1 .. 4
- *   flags        T-step kernel flags as in lbm_launch: 0, 2, 4 or 12
+ *   flags        T-step kernel flags as in lbm_launch: 0, 2, 4 or 12 (one
+ *                wave per strip task); or 32 or 34 (waves must be 4): one
+ *                workgroup per strip task, its four waves sharing the halo
+ *                columns through LDS as for lbm_launch variants 10-13 with
+ *                flag 32 (strips of 64 * 4 - 2(T-1) columns, rounded as
+ *                there; 34 also loads one row ahead).
  * The tile table holds the one-step tiles and, for T > 1, the strip tasks
  * of every unfinished member. */
 typedef struct lbm_pool_shape {
@@ -364,7 +369,8 @@ LBM_API size_t lbm_pool_workspace_bytes(int32_t max_members, int32_t max_tiles);
 /* Creates a pool.  dev_ws: device pointer, 256-byte aligned, at least
  * lbm_pool_workspace_bytes bytes, owned by the caller; stream: the pool's
  * hipStream_t.  Allocates pinned host staging for the tables.  Initial
- * shape {256, 512, 4096, 256, 7, 64, 4, 12} (seven steps per launch). */
+ * shape {256, 512, 4096, 256, 7, 64, 4, 32} (seven steps per launch, one
+ * workgroup of four waves per strip task). */
 LBM_API lbm_status lbm_pool_create(void *dev_ws, size_t ws_bytes, void *stream, int32_t max_members,
                                    int32_t max_tiles, lbm_pool **out);
 /* Returns every member to its lattice (as lbm_pool_remove) and frees the

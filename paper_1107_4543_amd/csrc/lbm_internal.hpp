@@ -79,7 +79,8 @@ struct PoolMember {
 
 // A tile of one member: rows y0 .. y0+nrows-1, columns x0 .. x0+ncols-1
 // (whole rows when the lattice is narrower than the tile size, otherwise a
-// segment of one row).
+// segment of one row).  T-step strip tasks use the same record (one wave
+// each, or with the shared halo one workgroup each).
 struct PoolTile {
     int32_t member, y0, x0, nrows, ncols, pad0, pad1, pad2;
 };

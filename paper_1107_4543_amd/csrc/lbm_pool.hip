@@ -76,7 +76,7 @@ struct lbm_pool {
     int ntiles = 0;
     int max_class_tiles = 0;         // largest one-step tile range of one class
     int max_class_tasks = 0;         // largest T-step task range of one class
-    lbm_pool_shape shape{256, 512, 4096, 256, 7, 64, 4, 12};
+    lbm_pool_shape shape{256, 512, 4096, 256, 7, 64, 4, 32};
     std::vector<Slot> slots;
     std::vector<int> finishing;      // slot indices in completion order
     std::map<std::tuple<unsigned, int, int, int, int, int>, GraphEntry> graphs;   // (class mask, steps, steps per T-step launch, one-step launches, grids)
@@ -99,10 +99,25 @@ int tile_cols(const lbm_pool_shape &sh, const lbm_lattice *L)
 }
 
 // T-step strip tasks: multi_strip_cols output columns by seg_rows rows.
-int strip_cols(const lbm_pool_shape &sh, const lbm_lattice *L)
+int elem_bytes(const lbm_lattice *L)
 {
     static const int bytes[4] = {8, 4, 2, 2};   // storage element size by lbm_storage
-    return lbm::multi_strip_cols(sh.steps_per_launch, bytes[L->v.storage]);
+    return bytes[L->v.storage];
+}
+
+int strip_cols(const lbm_pool_shape &sh, const lbm_lattice *L)
+{
+    return lbm::multi_strip_cols(sh.steps_per_launch, elem_bytes(L));
+}
+
+// Shared-halo tables (flags bit 5): strip tasks of one workgroup of
+// kWgMaxWaves waves each, as wide as its lanes allow.
+bool wg_table(const lbm_pool_shape &sh) { return sh.steps_per_launch > 1 && (sh.flags & lbm::kWgHalo) != 0; }
+
+int task_cols(const lbm_pool_shape &sh, const lbm_lattice *L)
+{
+    return wg_table(sh) ? lbm::multi_strip_cols(sh.steps_per_launch, elem_bytes(L), 64 * lbm::kWgMaxWaves)
+                        : strip_cols(sh, L);
 }
 
 // Segments of a member's strips: the ny rows cut into k = max(1, round(ny
@@ -116,7 +131,7 @@ int segments_of(const lbm_pool_shape &sh, const lbm_lattice *L)
 int tasks_of(const lbm_pool_shape &sh, const lbm_lattice *L)
 {
     if (sh.steps_per_launch < 2) return 0;
-    const int w = strip_cols(sh, L);
+    const int w = task_cols(sh, L);
     return ((L->v.nx + w - 1) / w) * segments_of(sh, L);
 }
 
@@ -190,7 +205,7 @@ lbm_status upload(lbm_pool *P)
                 all.push_back(t);
             }
         if (P->shape.steps_per_launch > 1) {
-            const int w = strip_cols(P->shape, L), k = segments_of(P->shape, L);
+            const int w = task_cols(P->shape, L), k = segments_of(P->shape, L);
             for (int sg = 0; sg < k; ++sg) {
                 const int y0 = (int)((int64_t)L->v.ny * sg / k), y1 = (int)((int64_t)L->v.ny * (sg + 1) / k);
                 for (int x0 = 0; x0 < L->v.nx; x0 += w) {
@@ -201,22 +216,22 @@ lbm_status upload(lbm_pool *P)
                     t.t.x0 = x0;
                     t.t.nrows = y1 - y0;
                     t.t.ncols = std::min(w, L->v.nx - x0);
-                    // a wave's time follows its rows (every lane works, a
-                    // partial strip or not)
+                    // a wave's (workgroup's) time follows its rows (every
+                    // lane works, a partial strip or not)
                     t.cells = (int64_t)t.t.nrows * 64;
                     tasks.push_back(t);
                 }
             }
         }
     }
-    if ((int)(all.size() + tasks.size()) > P->max_tiles)
-        return pfail(LBM_E_NOMEM, "pool needs %zu tiles, has %d", all.size() + tasks.size(), P->max_tiles);
     // group by class, longest first (the hardware starts workgroups in
     // order, so the short tasks fill the end of the launch); one-step tiles,
     // then T-step tasks
     auto order = [](const T &a, const T &b) { return a.cls != b.cls ? a.cls < b.cls : a.cells > b.cells; };
     std::stable_sort(all.begin(), all.end(), order);
     std::stable_sort(tasks.begin(), tasks.end(), order);
+    if ((int)(all.size() + tasks.size()) > P->max_tiles)
+        return pfail(LBM_E_NOMEM, "pool needs %zu tiles, has %d", all.size() + tasks.size(), P->max_tiles);
     unsigned mask = 0;
     for (int c = 0; c < lbm::kClasses; ++c) hdr->begin[c] = hdr->end[c] = hdr->mbegin[c] = hdr->mend[c] = 0;
     for (size_t j = 0; j < all.size(); ++j) {
@@ -260,11 +275,13 @@ int launch_grid(const lbm_pool *P)
     return std::min(g, P->shape.grid);
 }
 
-// Workgroups of a T-step launch: enough waves for the largest class's
-// tasks, rounded up to a power of two, at most the shape's grid.
+// Workgroups of a T-step launch: enough waves (workgroups, in a shared-halo
+// table) for the largest class's tasks, rounded up to a power of two, at
+// most the shape's grid.
 int multi_grid(const lbm_pool *P)
 {
-    const int need = (P->max_class_tasks + P->shape.waves - 1) / P->shape.waves;
+    const int per = wg_table(P->shape) ? 1 : P->shape.waves;
+    const int need = (P->max_class_tasks + per - 1) / per;
     int g = 1;
     while (g < need && g < P->shape.grid) g *= 2;
     return std::min(g, P->shape.grid);
@@ -397,6 +414,7 @@ bool valid_shape(const lbm_pool_shape &s)
                           ((s.steps_per_launch == 2 || s.steps_per_launch == 4 || s.steps_per_launch == 5 ||
                             s.steps_per_launch == 6 || s.steps_per_launch == 7) && s.seg_rows >= 1 &&
                            s.seg_rows <= 4096 && s.waves >= 1 && s.waves <= 4 &&
+                           (!(s.flags & lbm::kWgHalo) || s.waves == lbm::kWgMaxWaves) &&
                            lbm::pool_multi_kernel(LBM_STORE_F32 * 2 + LBM_COMPUTE_F32, s.steps_per_launch, s.flags));
     return s.tile_cells >= 64 && s.tile_cells <= (1 << 22) && s.block >= 64 && s.block <= 1024 && s.block % 64 == 0 &&
            s.grid >= 1 && s.grid <= (1 << 20) && s.graph_steps >= 1 && s.graph_steps <= 1024 && multi_ok;
@@ -731,7 +749,7 @@ lbm_status lbm_pool_tune(lbm_pool *pool, int32_t reps, lbm_pool_shape *best, dou
     for (int T : {2, 4, 5, 6, 7})
         for (int seg : {32, 48, 64, 80, 128})
             for (int waves : {1, 4})
-                for (int flags : {0, 2, 12})
+                for (int flags : {0, 2, 12, 32, 34})           // 32, 34: four waves only
                     for (int grid : {4096, 16384, 65536}) {
                         lbm_pool_shape s = single;
                         s.steps_per_launch = T;

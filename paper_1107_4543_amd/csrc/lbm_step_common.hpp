@@ -358,8 +358,8 @@ __device__ __forceinline__ bool one_resource(int64_t plane)
 // boundary suffices as long as a barrier separates every read of it from
 // its next write: boundary b > 0 is rewritten after boundary b - 1's
 // barrier of the next row, boundary 0 after the next stage's barrier of the
-// same row (every prologue row also starts with a barrier, for the rows
-// that run no second exchange).
+// same row (every prologue row, and with T = 2 every row, also starts with a
+// barrier, for the rows that run no second exchange).
 
 // T steps of the strip whose cols output columns start at x0, rows y0 ..
 // y0+len-1 of one lattice.  Without the shared halo the calling wave owns
@@ -497,11 +497,12 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
         if constexpr (WG) {
             // Stage boundary 0 is written again at the start of every row,
             // so a barrier must separate the previous row's reads of it
-            // from this row's writes.  A steady row has one after those
-            // reads (the next stage's exchange); a prologue row that runs
-            // stage 0 and 1 only (rows 0 and 1) has none, so the rows after
-            // them start with one.
-            if (!STEADY && j >= 1) __syncthreads();
+            // from this row's writes.  A steady row with T > 2 has one after
+            // those reads (the next stage's exchange); a prologue row that
+            // runs stage 0 and 1 only (rows 0 and 1), and every row with
+            // T = 2 (one boundary), has none, so the rows after them start
+            // with one.
+            if (j >= 1 && (!STEADY || T == 2)) __syncthreads();
         }
 #pragma unroll
         for (int p = 1; p < T; ++p) {
@@ -744,23 +745,46 @@ __device__ __forceinline__ Relax<float> member_relax<float>(const PoolMember *m)
 template <>
 __device__ __forceinline__ Relax<double> member_relax<double>(const PoolMember *m) { return m->rd; }
 
-// T-step launch j of a chunk: each wave takes strip tasks of the class in
-// turn; a member takes T-step launches while T more steps fit.
+// T-step launch j of a chunk: a member takes T-step launches while T more
+// steps fit.  Without the shared halo each wave takes strip tasks of the
+// class in turn; with it (FLAGS bit 5, blockDim.y == kWgMaxWaves) each
+// workgroup does, its waves sharing the halo columns through LDS.  The
+// tables are read-only here: restrict lets the compiler read the task and
+// member records with scalar loads, so their fields take no vector
+// registers.
 template <typename S, typename C, int T, int FLAGS>
-__global__ void __launch_bounds__(256) k_pool_multi(const PoolHeader *hdr, const PoolMember *mem,
-                                                    const PoolTile *tiles, int cls, int j)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(multi_waves_per_eu<S, FLAGS>())))
+k_pool_multi(const PoolHeader *__restrict__ hdr, const PoolMember *__restrict__ mem,
+             const PoolTile *__restrict__ tiles, int cls, int j)
 {
     const int begin = hdr->mbegin[cls], end = hdr->mend[cls];
-    const int nw = (int)(gridDim.x * blockDim.y);
-    const int w0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * blockDim.y + threadIdx.y));   // one wave per task
-    for (int ti = begin + w0; ti < end; ti += nw) {
-        const PoolTile tile = tiles[ti];                 // wave-uniform
-        const PoolMember *m = mem + tile.member;
-        if ((int64_t)(j + 1) * T > m->t_target - m->t_done) continue;
-        const int par = (int)((m->cur0 + m->flips + j) & 1);
-        strip_pass<S, C, T, FLAGS, false>((const char *)m->buf[par], (char *)m->buf[par ^ 1], m->nx, m->ny, m->pitch,
-                                          m->plane, member_relax<C>(m), m->scale, m->inv_scale, tile.x0, tile.ncols,
-                                          tile.y0, tile.nrows);
+    if constexpr ((FLAGS & kWgHalo) != 0) {
+        __shared__ typename Store<S>::wide wgx[wg_exchange_values<T, FLAGS>()];
+        for (int ti = begin + (int)blockIdx.x; ti < end; ti += (int)gridDim.x) {
+            const PoolTile tile = tiles[ti];             // workgroup-uniform
+            const PoolMember *m = mem + tile.member;
+            if ((int64_t)(j + 1) * T > m->t_target - m->t_done) continue;
+            const int par = (int)((m->cur0 + m->flips + j) & 1);
+            strip_pass<S, C, T, FLAGS, false>((const char *)m->buf[par], (char *)m->buf[par ^ 1], m->nx, m->ny,
+                                              m->pitch, m->plane, member_relax<C>(m), m->scale, m->inv_scale, tile.x0,
+                                              tile.ncols, tile.y0, tile.nrows, wgx);
+            // every wave's reads of this task's last exchange (which reach
+            // into the neighbouring waves' columns) end before any wave
+            // writes the next task's
+            __syncthreads();
+        }
+    } else {
+        const int nw = (int)(gridDim.x * blockDim.y);
+        const int w0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * blockDim.y + threadIdx.y));   // one wave per task
+        for (int ti = begin + w0; ti < end; ti += nw) {
+            const PoolTile tile = tiles[ti];             // wave-uniform
+            const PoolMember *m = mem + tile.member;
+            if ((int64_t)(j + 1) * T > m->t_target - m->t_done) continue;
+            const int par = (int)((m->cur0 + m->flips + j) & 1);
+            strip_pass<S, C, T, FLAGS, false>((const char *)m->buf[par], (char *)m->buf[par ^ 1], m->nx, m->ny,
+                                              m->pitch, m->plane, member_relax<C>(m), m->scale, m->inv_scale, tile.x0,
+                                              tile.ncols, tile.y0, tile.nrows);
+        }
     }
 }
 

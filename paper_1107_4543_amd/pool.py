@@ -62,11 +62,13 @@ class Pool:
         return _lib.lbm_pool_get_shape(self._h).as_dict()
 
     def set_shape(self, tile_cells=256, block=512, grid=4096, graph_steps=256, steps_per_launch=7, seg_rows=64,
-                  waves=4, flags=12):
+                  waves=4, flags=32):
         """steps_per_launch 1 advances every member one step per launch over
         tiles of about tile_cells cells; 2, 4, 5, 6 or 7 uses strip tasks of the
         several-steps-per-pass kernel (seg_rows rows, `waves` waves per
-        workgroup, kernel flags 0, 2, 4 or 12 as for Lattice.set_launch)."""
+        workgroup, kernel flags 0, 2, 4 or 12 as for Lattice.set_launch, or
+        32 / 34 with four waves: one workgroup per strip task, halo columns
+        shared through LDS)."""
         _lib.lbm_pool_set_shape(self._h, _lib.lbm_pool_shape(tile_cells, block, grid, graph_steps, steps_per_launch,
                                                              seg_rows, waves, flags))
         return self

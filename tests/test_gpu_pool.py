@@ -177,3 +177,61 @@ def test_full_batch_of_256_lattices_matches_alone_on_a_sample():
         st, d = lats[j].diagnostics()
         assert st == 0
     pool.close()
+
+
+# Shared-halo tables (flags bit 5): every strip task is one workgroup of four
+# waves that pass their halo values through LDS.  Widths around the
+# workgroup strip (244 columns at T = 7 for 32-bit storage): an exact strip,
+# strips plus a narrow remainder, members narrower than a strip (whose lanes
+# wrap around the lattice) and a one-column member.
+WG_SIZES = [(600, 70), (200, 45), (257, 64), (64, 64), (1, 9), (490, 33), (244, 20), (31, 150), (1100, 12)]
+WG_STORES = ["f32", "f16", "f32", "bf16", "f32", "f64", "f32", "f16", "f32"]
+WG_STEPS = [37, 50, 23, 64, 5, 44, 71, 30, 19]
+WG_SCHEDULES = [dict(steps_per_launch=7, seg_rows=13, waves=4, flags=32),
+                   dict(steps_per_launch=7, seg_rows=40, waves=4, flags=34),
+                   dict(steps_per_launch=6, seg_rows=9, waves=4, flags=32),
+                   dict(steps_per_launch=4, seg_rows=16, waves=4, flags=34),
+                   dict(steps_per_launch=2, seg_rows=5, waves=4, flags=32)]
+
+
+@pytest.mark.parametrize("sched", WG_SCHEDULES)
+def test_shared_halo_tables_match_alone_bitwise(sched):
+    from paper_1107_4543_amd.pool import Pool
+    pool = Pool(max_members=16, max_tiles=1 << 14)
+    # grid 32: a workgroup walks several tasks in turn
+    pool.set_shape(tile_cells=512, block=256, grid=32, graph_steps=16, **sched)
+    lats, twins = [], []
+    for i, ((nx, ny), st, n) in enumerate(zip(WG_SIZES, WG_STORES, WG_STEPS)):
+        s = SETS[i % len(SETS)]
+        lat, f = make(nx, ny, s, st, seed=40 + i, u0=(0.02 * (i % 2), 0.0))
+        lat.step(2)
+        pool.add(lat, n)
+        lats.append(lat)
+        twins.append(twin(lat, f, s).step(2 + n))
+    pool.step(30)
+    pool.step(100)
+    torch.cuda.synchronize()
+    out = []
+    while pool.members:
+        out += pool.poll(wait=True)
+    assert len(out) == len(lats)
+    for lat, tw, n in zip(lats, twins, WG_STEPS):
+        assert lat.t == 2 + n
+        assert torch.equal(lat.populations(), tw.populations()), (lat.nx, lat.ny, lat.storage, sched)
+    pool.close()
+
+
+def test_shared_halo_table_member_parity_with_oracle_fp64():
+    from paper_1107_4543_amd.pool import Pool
+    pool = Pool(max_members=4, max_tiles=1024)
+    pool.set_shape(tile_cells=256, block=64, grid=16, graph_steps=14, steps_per_launch=7, seg_rows=11, waves=4,
+                   flags=32)
+    s = [1.64, 1.54, 1.9, float(linear.s_from_nu(1e-3))]
+    lat, (rho, ux, uy) = make(263, 30, s, "f64", seed=8, u0=(0.03, 0.0))
+    pool.add(lat, 33)
+    pool.step(33)
+    assert pool.poll(wait=True) == [lat]
+    ref = oracle.run(oracle.init(rho, ux, uy), s, 33)
+    f = lat.populations().cpu().numpy()
+    assert np.max(np.abs(f - ref)) <= 1e-12 * np.max(np.abs(ref))
+    pool.close()
