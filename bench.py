@@ -16,7 +16,8 @@ Prints one JSON line: MLUPS, the roofline of the step kernel over its
 measured average launch duration -- for one step per launch the HBM bound
 (algorithmic bytes 2 * 9 * sizeof(storage) per cell and launch against the
 8 TB/s peak); for several steps per launch the vector-ALU bound (the
-collision's 71 algorithmic operations per cell and step against the
+collision's 70 (FP32, FP64) or 71 (16-bit storage) algorithmic operations
+per cell and step against the
 non-packed issue peak), with the HBM figures beside it -- measured HBM
 traffic from the committed rocprofv3 counter summary when it matches the
 current kernel source, and the FP64 CPU oracle timed on a bounded sample of
@@ -52,14 +53,20 @@ def kernel_source_hash():
 
 
 VALU_PEAK = 256 * 4 * 16 * 2.4e9      # VALU lane-instructions per second (non-packed)
-# Arithmetic of one lattice update in the compute type: the folded collision's
-# 70 additions, multiplications and fused multiply-adds plus its reciprocal
-# (the moment sums, equilibrium numerators, relaxation, M^T and the
-# increment; the kernels' comments list them).  Vector-ALU peaks in
-# operations per second: one operation per lane and clock on 256 CUs x 4
-# SIMDs x 16 lanes at 2.4 GHz in FP32 (packed FP32 is not used), half that in
-# FP64.
-ALG_OPS_PER_LU = 71
+# Arithmetic of one lattice update in the compute type: the folded
+# collision's additions, multiplications and fused multiply-adds plus its
+# reciprocal (the moment sums, equilibrium numerators, relaxation, M^T and
+# the increment; the kernels' comments list them): 69 + 1 where the storage
+# type is the compute type (FP32, FP64: the rest population's update is one
+# multiply-add), 70 + 1 otherwise (16-bit storage, FP64 storage with FP32
+# collide: the rest population's increment is formed, then added).
+# Vector-ALU peaks in operations per second: one operation per lane and clock
+# on 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz in FP32 (packed FP32 is not
+# used), half that in FP64.
+def alg_ops_per_lu(storage, compute):
+    return 70 if storage == compute else 71
+
+
 ALU_PEAK = {"f32": 256 * 4 * 16 * 2.4e9, "f64": 256 * 4 * 16 * 2.4e9 / 2}
 
 
@@ -217,9 +224,10 @@ def read_pool_traffic(shape):
 
 def pool_roofline(T, cells, launches, ms, traffic=None, steps=None):
     """Roofline of the pool's step kernel over a timed pass of `steps` steps
-    that each member takes in `launches` launches: HBM for one step per
-    launch, the vector ALU (algorithmic operations, FP32) for T > 1, counting
-    the updates of the steps actually run."""
+    that each member (FP32 storage and collide) takes in `launches` launches:
+    HBM for one step per launch, the vector ALU (algorithmic operations,
+    FP32) for T > 1, counting the updates of the steps actually run."""
+    ops_lu = alg_ops_per_lu("f32", "f32")
     us = 1e3 * ms / launches
     gbps = 72 * cells / (us * 1e-6) / 1e9
     hbm = {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -230,13 +238,13 @@ def pool_roofline(T, cells, launches, ms, traffic=None, steps=None):
     if T == 1:
         return dict(hbm, **common)
     steps = launches * T if steps is None else steps
-    ops = ALG_OPS_PER_LU * cells * steps
+    ops = ops_lu * cells * steps
     tops = ops / (ms * 1e-3) / 1e12
     peak = ALU_PEAK["f32"] / 1e12
     return dict({"bound": "alu", "achieved": round(tops, 2), "peak": round(peak, 2), "unit": "T F32 ops/s",
                  "frac": round(tops / peak, 4), "traffic": traffic,
                  "algorithmic_ops_per_launch": round(ops / launches), "algorithmic_ops_timed": ops,
-                 "ops_per_update": ALG_OPS_PER_LU, "hbm": hbm}, **common)
+                 "ops_per_update": ops_lu, "hbm": hbm}, **common)
 
 
 # Pool shape measured fastest for batch256 on MI355X (seven steps per launch,
@@ -492,7 +500,7 @@ def bench_pulses8192(args):
         bpl = 18 * STORE_BYTES[storage] * launches / T
         gbps = 18 * STORE_BYTES[storage] * nx * ny * launches / (ms / 1e3) / 1e9
         mlups_r = nx * ny * T / (ms / 1e3) / 1e6
-        alu_tops = ALG_OPS_PER_LU * mlups_r * 1e6 / 1e12
+        alu_tops = alg_ops_per_lu(storage, compute) * mlups_r * 1e6 / 1e12
         rows.append({"storage": storage, "compute": compute, "mlups": round(mlups_r, 1),
                      "alg_ops_TOPs": round(alu_tops, 2), "alu_frac": round(alu_tops * 1e12 / ALU_PEAK[compute], 4),
                      "bytes_per_lu": round(bpl, 3), "achieved_GBps": round(gbps, 1),
@@ -638,10 +646,11 @@ def main():
         peak = ALU_PEAK[compute] / 1e12
         # (fewer steps than one launch: the region's single shorter launch)
         us = 1e3 * ev[0].elapsed_time(ev[full]) / full if full else 1e3 * ms / launches
-        ops = ALG_OPS_PER_LU * cells * spl
+        ops_lu = alg_ops_per_lu(args.storage, compute)
+        ops = ops_lu * cells * spl
         tops = ops / (us * 1e-6) / 1e12
         # the same over the whole timed region, from the steps actually run
-        tops_all = ALG_OPS_PER_LU * cells * args.steps / (ms * 1e-3) / 1e12
+        tops_all = ops_lu * cells * args.steps / (ms * 1e-3) / 1e12
         achieved_b = alg_bytes / (us * 1e-6) / 1e9
         hbm = {"bound": "hbm", "achieved": round(achieved_b, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                "frac": round(achieved_b / HBM_PEAK_GBPS, 4), "traffic": traffic,
@@ -651,7 +660,7 @@ def main():
         out["roofline"] = {"bound": "alu", "achieved": round(tops, 2), "peak": round(peak, 2),
                            "unit": "T %s ops/s" % compute.upper(), "frac": round(tops / peak, 4),
                            "traffic": traffic, "algorithmic_ops_per_launch": ops,
-                           "ops_per_update": ALG_OPS_PER_LU,
+                           "ops_per_update": ops_lu,
                            "kernel": "k_step_multi (%d steps per pass)" % spl, "steps_per_launch": spl,
                            "launches_timed": full, "avg_launch_us": round(us, 3),
                            "timed_region": {"steps": args.steps, "launches": launches, "ms": round(ms, 4),

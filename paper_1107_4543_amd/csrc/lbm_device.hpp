@@ -158,7 +158,7 @@ __device__ __forceinline__ void collide_increment(const T g[9], const Relax<T> &
     const T B8 = fmad(r.lam_nu, x8, B), Bm8 = fmad(-r.lam_nu, x8, B);
     const T q2 = T(2) * r.lam_q;
     const T s56 = x5 + x6, d56 = x5 - x6;
-    dg[0] = T(4) * (a4 - a3);
+    dg[0] = a4 - a3;                                    // a quarter of the rest population's increment
     dg[1] = fmad(-q2, x5, A7);
     dg[2] = fmad(-q2, x6, Am7);
     dg[3] = fmad(q2, x5, A7);

@@ -110,8 +110,18 @@ __device__ __forceinline__ void cell_update(typename Store<S>::wide w[9], const 
 #pragma unroll
     for (int i = 0; i < 9; ++i) g[i] = (C)w[i];
     collide_increment<C>(g, r, Store<S>::scaled ? (C)inv_scale : C(1), dg);
+    // The rest population's increment is 4 dg[0]; scaling by 4 is exact, so
+    // one multiply-add gives the same value as the product and the sum.  It
+    // is used where the sum is stored as it is (the storage type is the
+    // arithmetic type); before a narrowing to 16 bits the compiler could
+    // merge a multiply-add with the conversion, which rounds once instead
+    // of twice, so there the product and the sum stay separate operations.
+    if constexpr (std::is_same<W, C>::value && !Store<S>::scaled)
+        w[0] = fmad(C(4), dg[0], w[0]);
+    else
+        w[0] = w[0] + (W)(C(4) * dg[0]);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) w[i] = w[i] + (W)dg[i];
+    for (int i = 1; i < 9; ++i) w[i] = w[i] + (W)dg[i];
 }
 
 // ---- fused step -------------------------------------------------------------

@@ -63,14 +63,14 @@ def test_pool_roofline_bound_follows_the_steps_per_launch():
     assert abs(one["achieved"] - 72 * cells / (us * 1e-6) / 1e9) < 0.1
     assert abs(one["frac"] - one["achieved"] / bench.HBM_PEAK_GBPS) < 1e-4
     multi = bench.pool_roofline(7, cells, launches, ms)
-    assert multi["bound"] == "alu" and multi["ops_per_update"] == bench.ALG_OPS_PER_LU
-    assert multi["algorithmic_ops_per_launch"] == bench.ALG_OPS_PER_LU * cells * 7
-    assert abs(multi["achieved"] - bench.ALG_OPS_PER_LU * cells * 7 / (us * 1e-6) / 1e12) < 0.01
+    assert multi["bound"] == "alu" and multi["ops_per_update"] == bench.alg_ops_per_lu("f32", "f32")
+    assert multi["algorithmic_ops_per_launch"] == bench.alg_ops_per_lu("f32", "f32") * cells * 7
+    assert abs(multi["achieved"] - bench.alg_ops_per_lu("f32", "f32") * cells * 7 / (us * 1e-6) / 1e12) < 0.01
     # with the steps actually run given (67 steps in 10 launches of at most
     # 7), the operations are those of 67 steps, not 70
     part = bench.pool_roofline(7, cells, launches, ms, steps=67)
-    assert part["algorithmic_ops_timed"] == bench.ALG_OPS_PER_LU * cells * 67
-    assert abs(part["achieved"] - bench.ALG_OPS_PER_LU * cells * 67 / (ms * 1e-3) / 1e12) < 0.01
+    assert part["algorithmic_ops_timed"] == bench.alg_ops_per_lu("f32", "f32") * cells * 67
+    assert abs(part["achieved"] - bench.alg_ops_per_lu("f32", "f32") * cells * 67 / (ms * 1e-3) / 1e12) < 0.01
     assert abs(multi["peak"] - 39.32) < 0.01 and 0 < multi["frac"] < 1
     assert multi["hbm"]["achieved"] == one["achieved"]
     # the FP64 vector peak is half the FP32 one
