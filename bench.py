@@ -17,11 +17,10 @@ measured average launch duration -- for one step per launch the HBM bound
 (algorithmic bytes 2 * 9 * sizeof(storage) per cell and launch against the
 8 TB/s peak); for several steps per launch the vector-ALU bound (the
 collision's 70 (FP32, FP64) or 71 (16-bit storage) algorithmic operations
-per cell and step against the
-non-packed issue peak), with the HBM figures beside it -- measured HBM
-traffic from the committed rocprofv3 counter summary when it matches the
-current kernel source, and the FP64 CPU oracle timed on a bounded sample of
-the same workload on the host cores.
+per cell and step against the non-packed issue peak), with the HBM figures
+beside it -- measured HBM traffic from the committed rocprofv3 counter
+summary when it matches the current kernel source, and the FP64 CPU oracle
+timed on a bounded sample of the same workload on the host cores.
 """
 import argparse
 import hashlib
