@@ -247,9 +247,9 @@ def pool_roofline(T, cells, launches, ms, traffic=None, steps=None):
 
 
 # Pool shape measured fastest for batch256 on MI355X (seven steps per launch,
-# strip tasks of about 64 rows, one workgroup of 4 waves sharing its halo
+# strip tasks of about 96 rows, one workgroup of 4 waves sharing its halo
 # columns through LDS per task, flags 32; the pool's initial shape).
-DEFAULT_POOL_SHAPE = "256,512,4096,256,7,64,4,32"
+DEFAULT_POOL_SHAPE = "256,512,4096,256,7,96,4,32"
 POOL_SHAPE_KEYS = ["tile_cells", "block", "grid", "graph_steps", "steps_per_launch", "seg_rows", "waves", "flags"]
 
 

@@ -312,8 +312,11 @@ LBM_API int32_t lbm_steps_per_launch(const lbm_launch *cfg);
  * one-step launches; step loops of T 2^m steps up to graph_steps (at the
  * end of a run, the r < T remaining steps as one pass of r steps), each with
  * as many one-step launches as its members need, are recorded once as HIP
- * graphs and replayed
- * (lbm_pool_step(n) runs n steps as a few such replays).  Each
+ * graphs and replayed (lbm_pool_step(n) runs n steps as a few such replays).
+ * The members of a class are split into two groups of about equal cell
+ * counts whose launches form independent chains in the recorded loop
+ * (members never read each other's state), so the end of one group's
+ * launch overlaps the next launch of the other.  Each
  * member carries its own step count: a member added with nsteps stops after
  * exactly nsteps steps, independently of the others, and is then returned by
  * lbm_pool_poll.  Members join and leave between lbm_pool_step calls
@@ -369,7 +372,7 @@ LBM_API size_t lbm_pool_workspace_bytes(int32_t max_members, int32_t max_tiles);
 /* Creates a pool.  dev_ws: device pointer, 256-byte aligned, at least
  * lbm_pool_workspace_bytes bytes, owned by the caller; stream: the pool's
  * hipStream_t.  Allocates pinned host staging for the tables.  Initial
- * shape {256, 512, 4096, 256, 7, 64, 4, 32} (seven steps per launch, one
+ * shape {256, 512, 4096, 256, 7, 96, 4, 32} (seven steps per launch, one
  * workgroup of four waves per strip task). */
 LBM_API lbm_status lbm_pool_create(void *dev_ws, size_t ws_bytes, void *stream, int32_t max_members,
                                    int32_t max_tiles, lbm_pool **out);

@@ -62,6 +62,12 @@ hipError_t launch_set_node(const View &v, void *dst, int32_t x, int32_t y, doubl
 
 // Storage/compute class of a lattice: storage * 2 + compute (8 values).
 constexpr int kClasses = 8;
+// The members of one class are split into kChains groups whose launches form
+// independent chains in a recorded step loop (members never read each
+// other's state), so one group's launch can start while another's is still
+// ending.  Table range of a group: class * kChains + chain.
+constexpr int kChains = 2;
+constexpr int kRanges = kClasses * kChains;
 
 // Device-resident member record.  t_done advances on the device (commit
 // kernel) so that a recorded step loop stays valid while members come and go.
@@ -86,8 +92,8 @@ struct PoolTile {
 };
 
 struct PoolHeader {
-    int32_t begin[kClasses], end[kClasses];     // one-step tiles of each class
-    int32_t mbegin[kClasses], mend[kClasses];   // T-step strip tasks of each class
+    int32_t begin[kRanges], end[kRanges];       // one-step tiles of each range
+    int32_t mbegin[kRanges], mend[kRanges];     // T-step strip tasks of each range
 };
 
 // Launch schedule of a recorded chunk of kk steps with T steps per T-step
@@ -118,14 +124,15 @@ Relax<double> relax_f64(const View &v);
 
 // One-step launch i of a chunk of kk steps (schedule above) of every active
 // member of class cls.
-hipError_t launch_pool_step(int cls, const PoolHeader *hdr, const PoolMember *mem, const PoolTile *tiles, int i,
+hipError_t launch_pool_step(int range, const PoolHeader *hdr, const PoolMember *mem, const PoolTile *tiles, int i,
                             int kk, int T, int grid, int block, hipStream_t st);
-// T-step launch j of a chunk of every active member of class cls.
-hipError_t launch_pool_multi(int cls, int T, int flags, const PoolHeader *hdr, const PoolMember *mem,
+// T-step launch j of a chunk of every active member of table range `range`.
+hipError_t launch_pool_multi(int range, int T, int flags, const PoolHeader *hdr, const PoolMember *mem,
                              const PoolTile *tiles, int j, int grid, int waves, hipStream_t st);
 // t_done += span and flips += q + span - q T (schedule above) for members [0, nmem).
 hipError_t launch_pool_commit(PoolMember *mem, int nmem, int kk, int T, hipStream_t st);
-// Kernel entry points for graph nodes (nullptr if not instantiated).
+// Kernel entry points for graph nodes, by class (nullptr if not
+// instantiated); their range argument selects the table range.
 void *pool_step_kernel(int cls);
 void *pool_multi_kernel(int cls, int T, int flags);
 void *pool_commit_kernel();

@@ -317,11 +317,11 @@ __global__ void __launch_bounds__(1024) k_step_wide(StepArgs<C> a)
 
 template <typename S, typename C>
 __global__ void __launch_bounds__(1024) k_pool_step(const PoolHeader *hdr, const PoolMember *mem,
-                                                     const PoolTile *tiles, int cls, int i, int kk, int T)
+                                                     const PoolTile *tiles, int range, int i, int kk, int T)
 {
     using R = typename Store<S>::raw;
     using W = typename Store<S>::wide;
-    const int begin = hdr->begin[cls], end = hdr->end[cls];
+    const int begin = hdr->begin[range], end = hdr->end[range];
     for (int ti = begin + (int)blockIdx.x; ti < end; ti += (int)gridDim.x) {
         const PoolTile tile = tiles[ti];
         const PoolMember *m = mem + tile.member;
@@ -936,21 +936,21 @@ void *pool_multi_kernel(int cls, int T, int flags)
     }
 }
 
-hipError_t launch_pool_step(int cls, const PoolHeader *hdr, const PoolMember *mem, const PoolTile *tiles, int i,
+hipError_t launch_pool_step(int range, const PoolHeader *hdr, const PoolMember *mem, const PoolTile *tiles, int i,
                             int kk, int T, int grid, int block, hipStream_t st)
 {
-    void *f = pool_step_kernel(cls);
+    void *f = pool_step_kernel(range / kChains);
     if (!f) return hipErrorInvalidValue;
-    void *args[] = {(void *)&hdr, (void *)&mem, (void *)&tiles, (void *)&cls, (void *)&i, (void *)&kk, (void *)&T};
+    void *args[] = {(void *)&hdr, (void *)&mem, (void *)&tiles, (void *)&range, (void *)&i, (void *)&kk, (void *)&T};
     return hipLaunchKernel(f, dim3(grid), dim3(block), args, 0, st);
 }
 
-hipError_t launch_pool_multi(int cls, int T, int flags, const PoolHeader *hdr, const PoolMember *mem,
+hipError_t launch_pool_multi(int range, int T, int flags, const PoolHeader *hdr, const PoolMember *mem,
                              const PoolTile *tiles, int j, int grid, int waves, hipStream_t st)
 {
-    void *f = pool_multi_kernel(cls, T, flags);
+    void *f = pool_multi_kernel(range / kChains, T, flags);
     if (!f) return hipErrorInvalidValue;
-    void *args[] = {(void *)&hdr, (void *)&mem, (void *)&tiles, (void *)&cls, (void *)&j};
+    void *args[] = {(void *)&hdr, (void *)&mem, (void *)&tiles, (void *)&range, (void *)&j};
     return hipLaunchKernel(f, dim3(grid), dim3(64, waves), args, 0, st);
 }
 

@@ -72,14 +72,14 @@ struct lbm_pool {
     hipEvent_t ev_stage = nullptr;
     bool stage_pending = false;
     bool dirty = true;
-    unsigned class_mask = 0;         // classes with tiles in the uploaded tables
+    unsigned range_mask = 0;         // table ranges (class * kChains + chain) with tiles
     int ntiles = 0;
-    int max_class_tiles = 0;         // largest one-step tile range of one class
-    int max_class_tasks = 0;         // largest T-step task range of one class
-    lbm_pool_shape shape{256, 512, 4096, 256, 7, 64, 4, 32};
+    int max_range_tiles = 0;         // largest one-step tile range
+    int max_range_tasks = 0;         // largest T-step task range
+    lbm_pool_shape shape{256, 512, 4096, 256, 7, 96, 4, 32};
     std::vector<Slot> slots;
     std::vector<int> finishing;      // slot indices in completion order
-    std::map<std::tuple<unsigned, int, int, int, int, int>, GraphEntry> graphs;   // (class mask, steps, steps per T-step launch, one-step launches, grids)
+    std::map<std::tuple<unsigned, int, int, int, int, int>, GraphEntry> graphs;   // (range mask, steps, steps per T-step launch, one-step launches, grids)
 };
 
 namespace {
@@ -165,7 +165,27 @@ lbm_status upload(lbm_pool *P)
     lbm::PoolMember *mem = (lbm::PoolMember *)(base + ((char *)P->d_mem - P->ws));
     lbm::PoolTile *tiles = (lbm::PoolTile *)(base + ((char *)P->d_tiles - P->ws));
     memset(base, 0, (size_t)((char *)P->d_tiles - P->ws));
-    struct T { int cls; int64_t cells; lbm::PoolTile t; };
+    // Chains: the unfinished members of each class, largest first, each to
+    // the chain of that class with the fewest cells so far.
+    std::vector<int> chain(P->max_members, 0);
+    {
+        std::vector<std::pair<int64_t, int>> by_size;
+        for (int i = 0; i < P->max_members; ++i) {
+            const Slot &sl = P->slots[i];
+            if (sl.lat && sl.t_done < sl.t_target) by_size.push_back({-(int64_t)sl.lat->v.nx * sl.lat->v.ny, i});
+        }
+        std::sort(by_size.begin(), by_size.end());
+        int64_t load[lbm::kClasses][lbm::kChains] = {};
+        for (const auto &e : by_size) {
+            const int c = class_of(P->slots[e.second].lat);
+            int best = 0;
+            for (int k = 1; k < lbm::kChains; ++k)
+                if (load[c][k] < load[c][best]) best = k;
+            chain[e.second] = best;
+            load[c][best] -= e.first;
+        }
+    }
+    struct T { int range; int64_t cells; lbm::PoolTile t; };
     std::vector<T> all, tasks;
     for (int i = 0; i < P->max_members; ++i) {
         const Slot &s = P->slots[i];
@@ -195,7 +215,7 @@ lbm_status upload(lbm_pool *P)
         for (int y0 = 0; y0 < L->v.ny; y0 += r)
             for (int x0 = 0; x0 < L->v.nx; x0 += cw) {
                 T t{};
-                t.cls = m.cls;
+                t.range = m.cls * lbm::kChains + chain[i];
                 t.t.member = i;
                 t.t.y0 = y0;
                 t.t.x0 = x0;
@@ -210,7 +230,7 @@ lbm_status upload(lbm_pool *P)
                 const int y0 = (int)((int64_t)L->v.ny * sg / k), y1 = (int)((int64_t)L->v.ny * (sg + 1) / k);
                 for (int x0 = 0; x0 < L->v.nx; x0 += w) {
                     T t{};
-                    t.cls = m.cls;
+                    t.range = m.cls * lbm::kChains + chain[i];
                     t.t.member = i;
                     t.t.y0 = y0;
                     t.t.x0 = x0;
@@ -224,19 +244,20 @@ lbm_status upload(lbm_pool *P)
             }
         }
     }
-    // group by class, longest first (the hardware starts workgroups in
+    // group by range, longest first (the hardware starts workgroups in
     // order, so the short tasks fill the end of the launch); one-step tiles,
     // then T-step tasks
-    auto order = [](const T &a, const T &b) { return a.cls != b.cls ? a.cls < b.cls : a.cells > b.cells; };
+    auto order = [](const T &a, const T &b) { return a.range != b.range ? a.range < b.range : a.cells > b.cells; };
     std::stable_sort(all.begin(), all.end(), order);
     std::stable_sort(tasks.begin(), tasks.end(), order);
     if ((int)(all.size() + tasks.size()) > P->max_tiles)
         return pfail(LBM_E_NOMEM, "pool needs %zu tiles, has %d", all.size() + tasks.size(), P->max_tiles);
+    static_assert(lbm::kRanges <= 32, "range mask bits");
     unsigned mask = 0;
-    for (int c = 0; c < lbm::kClasses; ++c) hdr->begin[c] = hdr->end[c] = hdr->mbegin[c] = hdr->mend[c] = 0;
+    for (int c = 0; c < lbm::kRanges; ++c) hdr->begin[c] = hdr->end[c] = hdr->mbegin[c] = hdr->mend[c] = 0;
     for (size_t j = 0; j < all.size(); ++j) {
         tiles[j] = all[j].t;
-        const int c = all[j].cls;
+        const int c = all[j].range;
         if (!(mask & (1u << c))) hdr->begin[c] = (int)j;
         hdr->end[c] = (int)j + 1;
         mask |= 1u << c;
@@ -245,23 +266,23 @@ lbm_status upload(lbm_pool *P)
     for (size_t j = 0; j < tasks.size(); ++j) {
         const int at = (int)(all.size() + j);
         tiles[at] = tasks[j].t;
-        const int c = tasks[j].cls;
+        const int c = tasks[j].range;
         if (!(tmask & (1u << c))) hdr->mbegin[c] = at;
         hdr->mend[c] = at + 1;
         tmask |= 1u << c;
     }
     P->ntiles = (int)(all.size() + tasks.size());
-    P->max_class_tiles = P->max_class_tasks = 0;
-    for (int c = 0; c < lbm::kClasses; ++c) {
-        P->max_class_tiles = std::max(P->max_class_tiles, hdr->end[c] - hdr->begin[c]);
-        P->max_class_tasks = std::max(P->max_class_tasks, hdr->mend[c] - hdr->mbegin[c]);
+    P->max_range_tiles = P->max_range_tasks = 0;
+    for (int c = 0; c < lbm::kRanges; ++c) {
+        P->max_range_tiles = std::max(P->max_range_tiles, hdr->end[c] - hdr->begin[c]);
+        P->max_range_tasks = std::max(P->max_range_tasks, hdr->mend[c] - hdr->mbegin[c]);
     }
     const size_t used = (size_t)((char *)P->d_tiles - P->ws) + sizeof(lbm::PoolTile) * (size_t)P->ntiles;
     if ((e = hipMemcpyAsync(P->ws, P->stage, used, hipMemcpyHostToDevice, P->stream)) != hipSuccess)
         return phip(e, "hipMemcpyAsync (pool tables)");
     if ((e = hipEventRecord(P->ev_stage, P->stream)) != hipSuccess) return phip(e, "hipEventRecord");
     P->stage_pending = true;
-    P->class_mask = mask;
+    P->range_mask = mask;
     P->dirty = false;
     return LBM_OK;
 }
@@ -271,17 +292,17 @@ lbm_status upload(lbm_pool *P)
 int launch_grid(const lbm_pool *P)
 {
     int g = 1;
-    while (g < P->max_class_tiles && g < P->shape.grid) g *= 2;
+    while (g < P->max_range_tiles && g < P->shape.grid) g *= 2;
     return std::min(g, P->shape.grid);
 }
 
 // Workgroups of a T-step launch: enough waves (workgroups, in a shared-halo
-// table) for the largest class's tasks, rounded up to a power of two, at
+// table) for the largest range's tasks, rounded up to a power of two, at
 // most the shape's grid.
 int multi_grid(const lbm_pool *P)
 {
     const int per = wg_table(P->shape) ? 1 : P->shape.waves;
-    const int need = (P->max_class_tasks + per - 1) / per;
+    const int need = (P->max_range_tasks + per - 1) / per;
     int g = 1;
     while (g < need && g < P->shape.grid) g *= 2;
     return std::min(g, P->shape.grid);
@@ -289,10 +310,12 @@ int multi_grid(const lbm_pool *P)
 
 // Records a step loop of `len` steps: the chunk schedule of
 // lbm_internal.hpp (len / T T-step launches, then `nsingle` of its one-step
-// launches, one node per class in `mask`, each depending on the previous
-// launch), then the commit kernel.  The one-step launches a member takes in
-// the chunk come first, so nsingle only has to cover the largest such count
-// among the members.  T is the chunk's steps per T-step launch (chunk_steps).
+// launches, one node per table range in `mask`, each depending only on the
+// same range's previous launch: ranges hold disjoint members, so their
+// chains may overlap on the device), then the commit kernel after every
+// chain.  The one-step launches a member takes in the chunk come first, so
+// nsingle only has to cover the largest such count among the members.  T is
+// the chunk's steps per T-step launch (chunk_steps).
 lbm_status get_graph(lbm_pool *P, unsigned mask, int len, int T, int nsingle, hipGraphExec_t *out)
 {
     const int grid = launch_grid(P), mgrid = multi_grid(P);
@@ -305,19 +328,19 @@ lbm_status get_graph(lbm_pool *P, unsigned mask, int len, int T, int nsingle, hi
     GraphEntry g;
     hipError_t e;
     if ((e = hipGraphCreate(&g.graph, 0)) != hipSuccess) return phip(e, "hipGraphCreate");
-    std::vector<hipGraphNode_t> prev, cur;
+    hipGraphNode_t last[lbm::kRanges] = {};
     const lbm::PoolHeader *hdr = P->d_hdr;
     const lbm::PoolMember *mem = P->d_mem;
     const lbm::PoolTile *tiles = P->d_tiles;
     const int nmulti = lbm::chunk_multi_launches(len, T);
     for (int k = 0; k < nmulti + nsingle; ++k) {
-        cur.clear();
         const bool multi = k < nmulti;
-        for (int c = 0; c < lbm::kClasses; ++c) {
-            if (!(mask & (1u << c))) continue;
-            int cls = c, idx = multi ? k : k - nmulti, kk = len, TT = T;
-            void *margs[] = {(void *)&hdr, (void *)&mem, (void *)&tiles, (void *)&cls, (void *)&idx};
-            void *sargs[] = {(void *)&hdr, (void *)&mem, (void *)&tiles, (void *)&cls, (void *)&idx, (void *)&kk,
+        for (int r = 0; r < lbm::kRanges; ++r) {
+            if (!(mask & (1u << r))) continue;
+            const int c = r / lbm::kChains;
+            int range = r, idx = multi ? k : k - nmulti, kk = len, TT = T;
+            void *margs[] = {(void *)&hdr, (void *)&mem, (void *)&tiles, (void *)&range, (void *)&idx};
+            void *sargs[] = {(void *)&hdr, (void *)&mem, (void *)&tiles, (void *)&range, (void *)&idx, (void *)&kk,
                              (void *)&TT};
             hipKernelNodeParams np{};
             np.func = multi ? lbm::pool_multi_kernel(c, T, P->shape.flags) : lbm::pool_step_kernel(c);
@@ -327,16 +350,18 @@ lbm_status get_graph(lbm_pool *P, unsigned mask, int len, int T, int nsingle, hi
             np.kernelParams = multi ? margs : sargs;
             np.extra = nullptr;
             hipGraphNode_t n;
-            if (!np.func ||
-                (e = hipGraphAddKernelNode(&n, g.graph, prev.empty() ? nullptr : prev.data(), prev.size(), &np)) !=
-                    hipSuccess) {
+            if (!np.func || (e = hipGraphAddKernelNode(&n, g.graph, k ? &last[r] : nullptr, k ? 1 : 0, &np)) !=
+                                hipSuccess) {
                 (void)hipGraphDestroy(g.graph);
                 return np.func ? phip(e, "hipGraphAddKernelNode") : pfail(LBM_E_INVAL, "no pool kernel for this shape");
             }
-            cur.push_back(n);
+            last[r] = n;
         }
-        prev.swap(cur);
     }
+    std::vector<hipGraphNode_t> prev;
+    if (nmulti + nsingle > 0)
+        for (int r = 0; r < lbm::kRanges; ++r)
+            if (mask & (1u << r)) prev.push_back(last[r]);
     lbm::PoolMember *memw = P->d_mem;
     int nmem = P->max_members, kk = len, TT = T;
     void *cargs[] = {(void *)&memw, (void *)&nmem, (void *)&kk, (void *)&TT};
@@ -368,8 +393,8 @@ int chunk_steps(const lbm_pool *P, int kk)
 {
     const int T = P->shape.steps_per_launch;
     if (T < 2 || kk >= T || kk < 2) return T;
-    for (int c = 0; c < lbm::kClasses; ++c)
-        if ((P->class_mask & (1u << c)) && !lbm::pool_multi_kernel(c, kk, P->shape.flags)) return T;
+    for (int r = 0; r < lbm::kRanges; ++r)
+        if ((P->range_mask & (1u << r)) && !lbm::pool_multi_kernel(r / lbm::kChains, kk, P->shape.flags)) return T;
     return kk;
 }
 
@@ -388,7 +413,7 @@ lbm_status run_chunk(lbm_pool *P, int kk)
         need = std::max(need, std::min<int64_t>(rem, kk) - lbm::member_multi(rem, kk, T) * T);
     }
     need = std::min<int64_t>(need, lbm::chunk_single_launches(kk, T));
-    lbm_status st = get_graph(P, P->class_mask, kk, T, (int)need, &ex);
+    lbm_status st = get_graph(P, P->range_mask, kk, T, (int)need, &ex);
     if (st != LBM_OK) return st;
     if ((e = hipGraphLaunch(ex, P->stream)) != hipSuccess) return phip(e, "hipGraphLaunch");
     for (int i = 0; i < P->max_members; ++i) {
@@ -682,8 +707,8 @@ lbm_status lbm_pool_time_launches(lbm_pool *pool, int32_t reps, double *avg_us)
     // does not change.
     const int T = pool->shape.steps_per_launch;
     auto launch_all = [&]() -> hipError_t {
-        for (int c = 0; c < lbm::kClasses; ++c) {
-            if (!(pool->class_mask & (1u << c))) continue;
+        for (int c = 0; c < lbm::kRanges; ++c) {
+            if (!(pool->range_mask & (1u << c))) continue;
             hipError_t r = T > 1 ? lbm::launch_pool_multi(c, T, pool->shape.flags, pool->d_hdr, pool->d_mem,
                                                           pool->d_tiles, 0, multi_grid(pool), pool->shape.waves,
                                                           pool->stream)
@@ -747,7 +772,7 @@ lbm_status lbm_pool_tune(lbm_pool *pool, int32_t reps, lbm_pool_shape *best, dou
             }
     // several steps per launch (their left-over steps use the best one-step tiles)
     for (int T : {2, 4, 5, 6, 7})
-        for (int seg : {32, 48, 64, 80, 128})
+        for (int seg : {32, 48, 64, 96, 128})
             for (int waves : {1, 4})
                 for (int flags : {0, 2, 12, 32, 34})           // 32, 34: four waves only
                     for (int grid : {4096, 16384, 65536}) {

@@ -755,9 +755,9 @@ __device__ __forceinline__ Relax<float> member_relax<float>(const PoolMember *m)
 template <>
 __device__ __forceinline__ Relax<double> member_relax<double>(const PoolMember *m) { return m->rd; }
 
-// T-step launch j of a chunk: a member takes T-step launches while T more
-// steps fit.  Without the shared halo each wave takes strip tasks of the
-// class in turn; with it (FLAGS bit 5, blockDim.y == kWgMaxWaves) each
+// T-step launch j of a chunk over the tasks of one table range: a member
+// takes T-step launches while T more steps fit.  Without the shared halo each
+// wave takes strip tasks in turn; with it (FLAGS bit 5, blockDim.y == kWgMaxWaves) each
 // workgroup does, its waves sharing the halo columns through LDS.  The
 // tables are read-only here: restrict lets the compiler read the task and
 // member records with scalar loads, so their fields take no vector
@@ -765,9 +765,9 @@ __device__ __forceinline__ Relax<double> member_relax<double>(const PoolMember *
 template <typename S, typename C, int T, int FLAGS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(multi_waves_per_eu<S, FLAGS>())))
 k_pool_multi(const PoolHeader *__restrict__ hdr, const PoolMember *__restrict__ mem,
-             const PoolTile *__restrict__ tiles, int cls, int j)
+             const PoolTile *__restrict__ tiles, int range, int j)
 {
-    const int begin = hdr->mbegin[cls], end = hdr->mend[cls];
+    const int begin = hdr->mbegin[range], end = hdr->mend[range];
     if constexpr ((FLAGS & kWgHalo) != 0) {
         __shared__ typename Store<S>::wide wgx[wg_exchange_values<T, FLAGS>()];
         for (int ti = begin + (int)blockIdx.x; ti < end; ti += (int)gridDim.x) {

@@ -61,7 +61,7 @@ class Pool:
     def shape(self):
         return _lib.lbm_pool_get_shape(self._h).as_dict()
 
-    def set_shape(self, tile_cells=256, block=512, grid=4096, graph_steps=256, steps_per_launch=7, seg_rows=64,
+    def set_shape(self, tile_cells=256, block=512, grid=4096, graph_steps=256, steps_per_launch=7, seg_rows=96,
                   waves=4, flags=32):
         """steps_per_launch 1 advances every member one step per launch over
         tiles of about tile_cells cells; 2, 4, 5, 6 or 7 uses strip tasks of the
