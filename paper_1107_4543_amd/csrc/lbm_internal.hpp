@@ -24,6 +24,10 @@ struct View {
 
 constexpr int kWgHalo = 32;        // launch-flags bit of the workgroup-shared halo (variants 10-13)
 constexpr int kWgMaxWaves = 4;     // waves per workgroup it supports
+// With kWgHalo in a pool's T-step kernel: workgroups of two waves (strips of
+// 128 - 2(T-1) columns, for the columns a member has left over after its
+// four-wave strips); not a launch flag of a single lattice.
+constexpr int kWgTwo = 64;
 constexpr int kRedBlocks = 512;    // blocks of the two-pass reductions
 constexpr int kRedWidth = 20;      // max doubles per block partial
 constexpr size_t kScratchBytes = (size_t)kRedBlocks * kRedWidth * sizeof(double) + 64 * sizeof(double);
@@ -94,6 +98,7 @@ struct PoolTile {
 struct PoolHeader {
     int32_t begin[kRanges], end[kRanges];       // one-step tiles of each range
     int32_t mbegin[kRanges], mend[kRanges];     // T-step strip tasks of each range
+    int32_t hbegin[kRanges], hend[kRanges];     // T-step two-wave strip tasks (kWgTwo) of each range
 };
 
 // Launch schedule of a recorded chunk of kk steps with T steps per T-step

@@ -50,7 +50,8 @@ void *pool_multi_impl(int T, int flags)
 {
 #define LBM_PM(T_, F_) \
     if (T == T_ && flags == F_) return reinterpret_cast<void *>(&k_pool_multi<S, C, T_, F_>);
-#define LBM_PM_T(T_) LBM_PM(T_, 0) LBM_PM(T_, 2) LBM_PM(T_, 4) LBM_PM(T_, 12) LBM_PM(T_, 32) LBM_PM(T_, 34)
+#define LBM_PM_T(T_) LBM_PM(T_, 0) LBM_PM(T_, 2) LBM_PM(T_, 4) LBM_PM(T_, 12) LBM_PM(T_, 32) LBM_PM(T_, 34) \
+                     LBM_PM(T_, 96) LBM_PM(T_, 98)
     LBM_PM_T(2)
     LBM_PM_T(3)
     LBM_PM_T(4)

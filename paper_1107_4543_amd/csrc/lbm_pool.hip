@@ -74,12 +74,14 @@ struct lbm_pool {
     bool dirty = true;
     unsigned range_mask = 0;         // table ranges (class * kChains + chain) with tiles
     int ntiles = 0;
+    unsigned two_mask = 0;           // table ranges with two-wave strip tasks
     int max_range_tiles = 0;         // largest one-step tile range
     int max_range_tasks = 0;         // largest T-step task range
+    int max_range_two = 0;           // largest two-wave task range
     lbm_pool_shape shape{256, 512, 4096, 256, 7, 96, 4, 32};
     std::vector<Slot> slots;
     std::vector<int> finishing;      // slot indices in completion order
-    std::map<std::tuple<unsigned, int, int, int, int, int>, GraphEntry> graphs;   // (range mask, steps, steps per T-step launch, one-step launches, grids)
+    std::map<std::tuple<unsigned, unsigned, int, int, int, int, int, int>, GraphEntry> graphs;   // (range masks, steps, steps per T-step launch, one-step launches, grids)
 };
 
 namespace {
@@ -110,14 +112,35 @@ int strip_cols(const lbm_pool_shape &sh, const lbm_lattice *L)
     return lbm::multi_strip_cols(sh.steps_per_launch, elem_bytes(L));
 }
 
-// Shared-halo tables (flags bit 5): strip tasks of one workgroup of
-// kWgMaxWaves waves each, as wide as its lanes allow.
+// Shared-halo tables (flags bit 5): strip tasks of one workgroup each, as
+// wide as its lanes allow: workgroups of kWgMaxWaves waves over a member's
+// columns from x = 0, and one of two waves for the columns left over when
+// they fit its strip (else one more, narrower, four-wave strip).
 bool wg_table(const lbm_pool_shape &sh) { return sh.steps_per_launch > 1 && (sh.flags & lbm::kWgHalo) != 0; }
 
 int task_cols(const lbm_pool_shape &sh, const lbm_lattice *L)
 {
     return wg_table(sh) ? lbm::multi_strip_cols(sh.steps_per_launch, elem_bytes(L), 64 * lbm::kWgMaxWaves)
                         : strip_cols(sh, L);
+}
+
+// Strips of a member in a shared-halo table: n4 four-wave strips of w4
+// columns (the last may be narrower), then two = 0 or 1 two-wave strip of
+// the remaining columns.
+struct WgStrips {
+    int w4, n4, two;
+};
+
+WgStrips wg_strips(const lbm_pool_shape &sh, const lbm_lattice *L)
+{
+    WgStrips g;
+    g.w4 = task_cols(sh, L);
+    const int w2 = lbm::multi_strip_cols(sh.steps_per_launch, elem_bytes(L), 128);
+    g.n4 = L->v.nx / g.w4;
+    const int rem = L->v.nx - g.n4 * g.w4;
+    g.two = rem > 0 && rem <= w2;
+    if (rem > w2) ++g.n4;
+    return g;
 }
 
 // Segments of a member's strips: the ny rows cut into k = max(1, round(ny
@@ -131,6 +154,10 @@ int segments_of(const lbm_pool_shape &sh, const lbm_lattice *L)
 int tasks_of(const lbm_pool_shape &sh, const lbm_lattice *L)
 {
     if (sh.steps_per_launch < 2) return 0;
+    if (wg_table(sh)) {
+        const WgStrips g = wg_strips(sh, L);
+        return (g.n4 + g.two) * segments_of(sh, L);
+    }
     const int w = task_cols(sh, L);
     return ((L->v.nx + w - 1) / w) * segments_of(sh, L);
 }
@@ -186,7 +213,7 @@ lbm_status upload(lbm_pool *P)
         }
     }
     struct T { int range; int64_t cells; lbm::PoolTile t; };
-    std::vector<T> all, tasks;
+    std::vector<T> all, tasks, twos;
     for (int i = 0; i < P->max_members; ++i) {
         const Slot &s = P->slots[i];
         lbm::PoolMember &m = mem[i];
@@ -225,21 +252,25 @@ lbm_status upload(lbm_pool *P)
                 all.push_back(t);
             }
         if (P->shape.steps_per_launch > 1) {
+            // four-wave (or one-wave) strips, then a two-wave one
+            const bool wg = wg_table(P->shape);
+            const WgStrips g = wg ? wg_strips(P->shape, L) : WgStrips{0, 0, 0};
             const int w = task_cols(P->shape, L), k = segments_of(P->shape, L);
+            const int nfull = wg ? g.n4 : (L->v.nx + w - 1) / w;
             for (int sg = 0; sg < k; ++sg) {
                 const int y0 = (int)((int64_t)L->v.ny * sg / k), y1 = (int)((int64_t)L->v.ny * (sg + 1) / k);
-                for (int x0 = 0; x0 < L->v.nx; x0 += w) {
+                for (int q = 0; q < nfull + g.two; ++q) {
                     T t{};
                     t.range = m.cls * lbm::kChains + chain[i];
                     t.t.member = i;
                     t.t.y0 = y0;
-                    t.t.x0 = x0;
+                    t.t.x0 = q * w;
                     t.t.nrows = y1 - y0;
-                    t.t.ncols = std::min(w, L->v.nx - x0);
+                    t.t.ncols = std::min(w, L->v.nx - t.t.x0);
                     // a wave's (workgroup's) time follows its rows (every
                     // lane works, a partial strip or not)
                     t.cells = (int64_t)t.t.nrows * 64;
-                    tasks.push_back(t);
+                    (q < nfull ? tasks : twos).push_back(t);
                 }
             }
         }
@@ -250,11 +281,13 @@ lbm_status upload(lbm_pool *P)
     auto order = [](const T &a, const T &b) { return a.range != b.range ? a.range < b.range : a.cells > b.cells; };
     std::stable_sort(all.begin(), all.end(), order);
     std::stable_sort(tasks.begin(), tasks.end(), order);
-    if ((int)(all.size() + tasks.size()) > P->max_tiles)
-        return pfail(LBM_E_NOMEM, "pool needs %zu tiles, has %d", all.size() + tasks.size(), P->max_tiles);
+    std::stable_sort(twos.begin(), twos.end(), order);
+    const size_t ntot = all.size() + tasks.size() + twos.size();
+    if ((int64_t)ntot > P->max_tiles) return pfail(LBM_E_NOMEM, "pool needs %zu tiles, has %d", ntot, P->max_tiles);
     static_assert(lbm::kRanges <= 32, "range mask bits");
     unsigned mask = 0;
-    for (int c = 0; c < lbm::kRanges; ++c) hdr->begin[c] = hdr->end[c] = hdr->mbegin[c] = hdr->mend[c] = 0;
+    for (int c = 0; c < lbm::kRanges; ++c)
+        hdr->begin[c] = hdr->end[c] = hdr->mbegin[c] = hdr->mend[c] = hdr->hbegin[c] = hdr->hend[c] = 0;
     for (size_t j = 0; j < all.size(); ++j) {
         tiles[j] = all[j].t;
         const int c = all[j].range;
@@ -271,11 +304,21 @@ lbm_status upload(lbm_pool *P)
         hdr->mend[c] = at + 1;
         tmask |= 1u << c;
     }
-    P->ntiles = (int)(all.size() + tasks.size());
-    P->max_range_tiles = P->max_range_tasks = 0;
+    unsigned hmask = 0;
+    for (size_t j = 0; j < twos.size(); ++j) {
+        const int at = (int)(all.size() + tasks.size() + j);
+        tiles[at] = twos[j].t;
+        const int c = twos[j].range;
+        if (!(hmask & (1u << c))) hdr->hbegin[c] = at;
+        hdr->hend[c] = at + 1;
+        hmask |= 1u << c;
+    }
+    P->ntiles = (int)ntot;
+    P->max_range_tiles = P->max_range_tasks = P->max_range_two = 0;
     for (int c = 0; c < lbm::kRanges; ++c) {
         P->max_range_tiles = std::max(P->max_range_tiles, hdr->end[c] - hdr->begin[c]);
         P->max_range_tasks = std::max(P->max_range_tasks, hdr->mend[c] - hdr->mbegin[c]);
+        P->max_range_two = std::max(P->max_range_two, hdr->hend[c] - hdr->hbegin[c]);
     }
     const size_t used = (size_t)((char *)P->d_tiles - P->ws) + sizeof(lbm::PoolTile) * (size_t)P->ntiles;
     if ((e = hipMemcpyAsync(P->ws, P->stage, used, hipMemcpyHostToDevice, P->stream)) != hipSuccess)
@@ -283,6 +326,7 @@ lbm_status upload(lbm_pool *P)
     if ((e = hipEventRecord(P->ev_stage, P->stream)) != hipSuccess) return phip(e, "hipEventRecord");
     P->stage_pending = true;
     P->range_mask = mask;
+    P->two_mask = hmask;
     P->dirty = false;
     return LBM_OK;
 }
@@ -308,18 +352,29 @@ int multi_grid(const lbm_pool *P)
     return std::min(g, P->shape.grid);
 }
 
+// Workgroups of a two-wave launch: one per task of the largest range,
+// rounded up to a power of two, at most the shape's grid.
+int two_grid(const lbm_pool *P)
+{
+    int g = 1;
+    while (g < P->max_range_two && g < P->shape.grid) g *= 2;
+    return std::min(g, P->shape.grid);
+}
+
 // Records a step loop of `len` steps: the chunk schedule of
 // lbm_internal.hpp (len / T T-step launches, then `nsingle` of its one-step
-// launches, one node per table range in `mask`, each depending only on the
-// same range's previous launch: ranges hold disjoint members, so their
-// chains may overlap on the device), then the commit kernel after every
-// chain.  The one-step launches a member takes in the chunk come first, so
-// nsingle only has to cover the largest such count among the members.  T is
-// the chunk's steps per T-step launch (chunk_steps).
-lbm_status get_graph(lbm_pool *P, unsigned mask, int len, int T, int nsingle, hipGraphExec_t *out)
+// launches) for every table range in `mask`, each launch depending only on
+// the same range's previous launch: ranges hold disjoint members, so their
+// chains may overlap on the device.  A T-step launch of a range with
+// two-wave tasks (`two`) is two nodes, four- and two-wave workgroups, that
+// run side by side.  The commit kernel follows every chain.  The one-step
+// launches a member takes in the chunk come first, so nsingle only has to
+// cover the largest such count among the members.  T is the chunk's steps
+// per T-step launch (chunk_steps).
+lbm_status get_graph(lbm_pool *P, unsigned mask, unsigned two, int len, int T, int nsingle, hipGraphExec_t *out)
 {
-    const int grid = launch_grid(P), mgrid = multi_grid(P);
-    auto key = std::make_tuple(mask, len, T, nsingle, grid, mgrid);
+    const int grid = launch_grid(P), mgrid = multi_grid(P), tgrid = two_grid(P);
+    auto key = std::make_tuple(mask, two, len, T, nsingle, grid, mgrid, tgrid);
     auto it = P->graphs.find(key);
     if (it != P->graphs.end()) {
         *out = it->second.exec;
@@ -328,7 +383,7 @@ lbm_status get_graph(lbm_pool *P, unsigned mask, int len, int T, int nsingle, hi
     GraphEntry g;
     hipError_t e;
     if ((e = hipGraphCreate(&g.graph, 0)) != hipSuccess) return phip(e, "hipGraphCreate");
-    hipGraphNode_t last[lbm::kRanges] = {};
+    std::vector<hipGraphNode_t> last[lbm::kRanges], cur;
     const lbm::PoolHeader *hdr = P->d_hdr;
     const lbm::PoolMember *mem = P->d_mem;
     const lbm::PoolTile *tiles = P->d_tiles;
@@ -338,30 +393,37 @@ lbm_status get_graph(lbm_pool *P, unsigned mask, int len, int T, int nsingle, hi
         for (int r = 0; r < lbm::kRanges; ++r) {
             if (!(mask & (1u << r))) continue;
             const int c = r / lbm::kChains;
-            int range = r, idx = multi ? k : k - nmulti, kk = len, TT = T;
-            void *margs[] = {(void *)&hdr, (void *)&mem, (void *)&tiles, (void *)&range, (void *)&idx};
-            void *sargs[] = {(void *)&hdr, (void *)&mem, (void *)&tiles, (void *)&range, (void *)&idx, (void *)&kk,
-                             (void *)&TT};
-            hipKernelNodeParams np{};
-            np.func = multi ? lbm::pool_multi_kernel(c, T, P->shape.flags) : lbm::pool_step_kernel(c);
-            np.gridDim = dim3(multi ? mgrid : grid);
-            np.blockDim = multi ? dim3(64, P->shape.waves) : dim3(P->shape.block);
-            np.sharedMemBytes = 0;
-            np.kernelParams = multi ? margs : sargs;
-            np.extra = nullptr;
-            hipGraphNode_t n;
-            if (!np.func || (e = hipGraphAddKernelNode(&n, g.graph, k ? &last[r] : nullptr, k ? 1 : 0, &np)) !=
-                                hipSuccess) {
-                (void)hipGraphDestroy(g.graph);
-                return np.func ? phip(e, "hipGraphAddKernelNode") : pfail(LBM_E_INVAL, "no pool kernel for this shape");
+            cur.clear();
+            // kind 0: one-step, or T-step of one-wave / four-wave
+            // workgroups; kind 1: T-step of two-wave workgroups
+            for (int kind = 0; kind < (multi && (two & (1u << r)) ? 2 : 1); ++kind) {
+                int range = r, idx = multi ? k : k - nmulti, kk = len, TT = T;
+                void *margs[] = {(void *)&hdr, (void *)&mem, (void *)&tiles, (void *)&range, (void *)&idx};
+                void *sargs[] = {(void *)&hdr, (void *)&mem, (void *)&tiles, (void *)&range, (void *)&idx, (void *)&kk,
+                                 (void *)&TT};
+                hipKernelNodeParams np{};
+                np.func = !multi    ? lbm::pool_step_kernel(c)
+                          : kind    ? lbm::pool_multi_kernel(c, T, P->shape.flags | lbm::kWgTwo)
+                                    : lbm::pool_multi_kernel(c, T, P->shape.flags);
+                np.gridDim = dim3(!multi ? grid : kind ? tgrid : mgrid);
+                np.blockDim = !multi ? dim3(P->shape.block) : dim3(64, kind ? 2 : P->shape.waves);
+                np.sharedMemBytes = 0;
+                np.kernelParams = multi ? margs : sargs;
+                np.extra = nullptr;
+                hipGraphNode_t n;
+                if (!np.func || (e = hipGraphAddKernelNode(&n, g.graph, last[r].empty() ? nullptr : last[r].data(),
+                                                           last[r].size(), &np)) != hipSuccess) {
+                    (void)hipGraphDestroy(g.graph);
+                    return np.func ? phip(e, "hipGraphAddKernelNode")
+                                   : pfail(LBM_E_INVAL, "no pool kernel for this shape");
+                }
+                cur.push_back(n);
             }
-            last[r] = n;
+            last[r] = cur;
         }
     }
     std::vector<hipGraphNode_t> prev;
-    if (nmulti + nsingle > 0)
-        for (int r = 0; r < lbm::kRanges; ++r)
-            if (mask & (1u << r)) prev.push_back(last[r]);
+    for (int r = 0; r < lbm::kRanges; ++r) prev.insert(prev.end(), last[r].begin(), last[r].end());
     lbm::PoolMember *memw = P->d_mem;
     int nmem = P->max_members, kk = len, TT = T;
     void *cargs[] = {(void *)&memw, (void *)&nmem, (void *)&kk, (void *)&TT};
@@ -393,8 +455,12 @@ int chunk_steps(const lbm_pool *P, int kk)
 {
     const int T = P->shape.steps_per_launch;
     if (T < 2 || kk >= T || kk < 2) return T;
-    for (int r = 0; r < lbm::kRanges; ++r)
-        if ((P->range_mask & (1u << r)) && !lbm::pool_multi_kernel(r / lbm::kChains, kk, P->shape.flags)) return T;
+    for (int r = 0; r < lbm::kRanges; ++r) {
+        if (!(P->range_mask & (1u << r))) continue;
+        if (!lbm::pool_multi_kernel(r / lbm::kChains, kk, P->shape.flags)) return T;
+        if ((P->two_mask & (1u << r)) && !lbm::pool_multi_kernel(r / lbm::kChains, kk, P->shape.flags | lbm::kWgTwo))
+            return T;
+    }
     return kk;
 }
 
@@ -413,7 +479,7 @@ lbm_status run_chunk(lbm_pool *P, int kk)
         need = std::max(need, std::min<int64_t>(rem, kk) - lbm::member_multi(rem, kk, T) * T);
     }
     need = std::min<int64_t>(need, lbm::chunk_single_launches(kk, T));
-    lbm_status st = get_graph(P, P->range_mask, kk, T, (int)need, &ex);
+    lbm_status st = get_graph(P, P->range_mask, P->two_mask, kk, T, (int)need, &ex);
     if (st != LBM_OK) return st;
     if ((e = hipGraphLaunch(ex, P->stream)) != hipSuccess) return phip(e, "hipGraphLaunch");
     for (int i = 0; i < P->max_members; ++i) {
@@ -439,7 +505,11 @@ bool valid_shape(const lbm_pool_shape &s)
                           ((s.steps_per_launch == 2 || s.steps_per_launch == 4 || s.steps_per_launch == 5 ||
                             s.steps_per_launch == 6 || s.steps_per_launch == 7) && s.seg_rows >= 1 &&
                            s.seg_rows <= 4096 && s.waves >= 1 && s.waves <= 4 &&
-                           (!(s.flags & lbm::kWgHalo) || s.waves == lbm::kWgMaxWaves) &&
+                           (!(s.flags & lbm::kWgHalo) ||
+                            (s.waves == lbm::kWgMaxWaves &&
+                             lbm::pool_multi_kernel(LBM_STORE_F32 * 2 + LBM_COMPUTE_F32, s.steps_per_launch,
+                                                    s.flags | lbm::kWgTwo))) &&
+                           !(s.flags & lbm::kWgTwo) &&
                            lbm::pool_multi_kernel(LBM_STORE_F32 * 2 + LBM_COMPUTE_F32, s.steps_per_launch, s.flags));
     return s.tile_cells >= 64 && s.tile_cells <= (1 << 22) && s.block >= 64 && s.block <= 1024 && s.block % 64 == 0 &&
            s.grid >= 1 && s.grid <= (1 << 20) && s.graph_steps >= 1 && s.graph_steps <= 1024 && multi_ok;
@@ -714,6 +784,9 @@ lbm_status lbm_pool_time_launches(lbm_pool *pool, int32_t reps, double *avg_us)
                                                           pool->stream)
                                  : lbm::launch_pool_step(c, pool->d_hdr, pool->d_mem, pool->d_tiles, 0, 1, 1,
                                                          launch_grid(pool), pool->shape.block, pool->stream);
+            if (r == hipSuccess && T > 1 && (pool->two_mask & (1u << c)))
+                r = lbm::launch_pool_multi(c, T, pool->shape.flags | lbm::kWgTwo, pool->d_hdr, pool->d_mem,
+                                           pool->d_tiles, 0, two_grid(pool), 2, pool->stream);
             if (r != hipSuccess) return r;
         }
         return hipSuccess;

@@ -380,13 +380,18 @@ __device__ __forceinline__ bool one_resource(int64_t plane)
 // arguments.
 // LDS of the shared-halo exchange: [buffer][stage boundary b (output of
 // stage b)][value k (populations 1, 3, 5, 6, 7, 8)][column of the
-// workgroup's lanes]; one buffer for the plain pipeline, two (alternating
-// rows) for the skewed one.
+// workgroup's lanes (256, or 128 for two-wave workgroups)]; one buffer for
+// the plain pipeline, two (alternating rows) for the skewed one.
 constexpr int kWgXchCols = 64 * kWgMaxWaves;
+template <int FLAGS>
+constexpr int wg_xch_cols()
+{
+    return (FLAGS & kWgTwo) ? 128 : kWgXchCols;
+}
 template <int T, int FLAGS>
 constexpr int wg_exchange_values()
 {
-    return (FLAGS & kWgHalo) ? (T - 1) * 6 * kWgXchCols * ((FLAGS & 16) ? 2 : 1) : 1;
+    return (FLAGS & kWgHalo) ? (T - 1) * 6 * wg_xch_cols<FLAGS>() * ((FLAGS & 16) ? 2 : 1) : 1;
 }
 
 template <typename S, typename C, int T, int FLAGS, bool ONE_RSRC>
@@ -420,7 +425,7 @@ __device__ __forceinline__ void strip_pass(const char *__restrict__ src, char *_
     // shared-halo exchange rows (wgx, the kernel's LDS); the neighbour
     // columns are clamped at the workgroup's edges (those lanes' results are
     // not used)
-    constexpr int XW = kWgXchCols;
+    constexpr int XW = wg_xch_cols<FLAGS>();
     W *const xch = WG ? wgx : nullptr;
     const int lanes = WG ? 64 * (int)blockDim.y : 64;
     const int lcl = lc > 0 ? lc - 1 : 0, lcr = lc + 1 < lanes ? lc + 1 : lc;
@@ -757,19 +762,24 @@ __device__ __forceinline__ Relax<double> member_relax<double>(const PoolMember *
 
 // T-step launch j of a chunk over the tasks of one table range: a member
 // takes T-step launches while T more steps fit.  Without the shared halo each
-// wave takes strip tasks in turn; with it (FLAGS bit 5, blockDim.y == kWgMaxWaves) each
-// workgroup does, its waves sharing the halo columns through LDS.  The
-// tables are read-only here: restrict lets the compiler read the task and
-// member records with scalar loads, so their fields take no vector
-// registers.
+// wave takes strip tasks in turn; with it (FLAGS bit 5) each workgroup does,
+// its waves sharing the halo columns through LDS: four-wave workgroups
+// (blockDim.y == kWgMaxWaves) take the range's strip tasks, two-wave ones
+// (FLAGS bit 6, blockDim.y == 2) its two-wave tasks.  The tables are
+// read-only here: restrict lets the compiler read the task and member
+// records with scalar loads, so their fields take no vector registers.
 template <typename S, typename C, int T, int FLAGS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(multi_waves_per_eu<S, FLAGS>())))
 k_pool_multi(const PoolHeader *__restrict__ hdr, const PoolMember *__restrict__ mem,
              const PoolTile *__restrict__ tiles, int range, int j)
 {
-    const int begin = hdr->mbegin[range], end = hdr->mend[range];
+    constexpr bool TWO = (FLAGS & kWgTwo) != 0;
+    const int begin = TWO ? hdr->hbegin[range] : hdr->mbegin[range];
+    const int end = TWO ? hdr->hend[range] : hdr->mend[range];
     if constexpr ((FLAGS & kWgHalo) != 0) {
         __shared__ typename Store<S>::wide wgx[wg_exchange_values<T, FLAGS>()];
+        // the exchange rows hold the columns of exactly this many waves
+        if ((int)blockDim.y != (TWO ? 2 : kWgMaxWaves)) return;
         for (int ti = begin + (int)blockIdx.x; ti < end; ti += (int)gridDim.x) {
             const PoolTile tile = tiles[ti];             // workgroup-uniform
             const PoolMember *m = mem + tile.member;
