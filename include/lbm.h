@@ -349,10 +349,14 @@ typedef struct lbm_pool lbm_pool;
  *   waves        waves per workgroup of the T-step launch, 1 .. 4
  *   flags        T-step kernel flags as in lbm_launch: 0, 2, 4 or 12 (one
  *                wave per strip task); or 32 or 34 (waves must be 4): one
- *                workgroup per strip task, its four waves sharing the halo
+ *                workgroup per strip task, its waves sharing the halo
  *                columns through LDS as for lbm_launch variants 10-13 with
- *                flag 32 (strips of 64 * 4 - 2(T-1) columns, rounded as
- *                there; 34 also loads one row ahead).
+ *                flag 32 (34 also loads one row ahead): four-wave strips of
+ *                64 * 4 - 2(T-1) columns (rounded as there) from column 0,
+ *                and the columns left over in one two-wave strip (64 * 2 -
+ *                2(T-1) columns, rounded alike) when they fit it, else in
+ *                one more, narrower, four-wave strip.  The two-wave
+ *                workgroups run as a second launch beside the first.
  * The tile table holds the one-step tiles and, for T > 1, the strip tasks
  * of every unfinished member. */
 typedef struct lbm_pool_shape {
