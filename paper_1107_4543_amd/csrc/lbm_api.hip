@@ -18,7 +18,28 @@
 
 using lbm::View;
 
+namespace lbm {
+
+// Compute units of the current device (queried once per device; 256 on
+// MI355X).
+int device_cus()
+{
+    static int cus[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cus[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
+
+}  // namespace lbm
+
 namespace {
+
+using lbm::device_cus;
 
 thread_local std::string g_err;
 
@@ -97,21 +118,6 @@ lbm_launch default_single(const View &)
     c.rows = 1;
     c.xcd_remap = 1;
     return c;
-}
-
-// Compute units of the current device (queried once per device; 256 on
-// MI355X).
-int device_cus()
-{
-    static int cus[64];
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    if (!cus[dev]) {
-        int n = 0;
-        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
-        cus[dev] = n;
-    }
-    return cus[dev];
 }
 
 // Segment rows of a shared-halo shape (T steps, waves per workgroup) that

@@ -119,6 +119,9 @@ __host__ __device__ inline int64_t member_multi(int64_t rem, int kk, int T)
 // Sets the text returned by lbm_last_error() on the calling thread.
 void set_error_text(const char *msg);
 
+// Compute units of the current device (256 on MI355X).
+int device_cus();
+
 // Fills *v for a raw state of the lattice that desc describes (validated as
 // by lbm_create; 16-bit storage needs an explicit scale_exp).  Sets the
 // error text on failure.

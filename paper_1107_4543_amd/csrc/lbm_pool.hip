@@ -146,27 +146,65 @@ WgStrips wg_strips(const lbm_pool_shape &sh, const lbm_lattice *L)
 // Segments of a member's strips: the ny rows cut into k = max(1, round(ny
 // / seg_rows)) nearly equal segments (heights differ by at most one row), so
 // that no member ends in a short segment that pays a whole pipeline start-up.
-int segments_of(const lbm_pool_shape &sh, const lbm_lattice *L)
+int segments_of(int seg_rows, const lbm_lattice *L)
 {
-    return std::max(1, (L->v.ny + sh.seg_rows / 2) / sh.seg_rows);
+    return std::max(1, (L->v.ny + seg_rows / 2) / seg_rows);
+}
+
+// Strips of a member's T-step tasks (four- and two-wave ones in a
+// shared-halo table).
+int strips_of(const lbm_pool_shape &sh, const lbm_lattice *L)
+{
+    if (wg_table(sh)) {
+        const WgStrips g = wg_strips(sh, L);
+        return g.n4 + g.two;
+    }
+    const int w = task_cols(sh, L);
+    return (L->v.nx + w - 1) / w;
 }
 
 int tasks_of(const lbm_pool_shape &sh, const lbm_lattice *L)
 {
     if (sh.steps_per_launch < 2) return 0;
-    if (wg_table(sh)) {
-        const WgStrips g = wg_strips(sh, L);
-        return (g.n4 + g.two) * segments_of(sh, L);
-    }
-    const int w = task_cols(sh, L);
-    return ((L->v.nx + w - 1) / w) * segments_of(sh, L);
+    return strips_of(sh, L) * segments_of(sh.seg_rows, L);
 }
 
 // Table entries of one unfinished member: one-step tiles plus T-step tasks.
-int tiles_of(const lbm_pool_shape &sh, const lbm_lattice *L)
+int onestep_tiles_of(const lbm_pool_shape &sh, const lbm_lattice *L)
 {
     const int r = tile_rows(sh, L), c = tile_cols(sh, L);
-    return ((L->v.ny + r - 1) / r) * ((L->v.nx + c - 1) / c) + tasks_of(sh, L);
+    return ((L->v.ny + r - 1) / r) * ((L->v.nx + c - 1) / c);
+}
+
+int tiles_of(const lbm_pool_shape &sh, const lbm_lattice *L) { return onestep_tiles_of(sh, L) + tasks_of(sh, L); }
+
+// Segment height of a pool's table: the shape's seg_rows, or -- when the
+// unfinished members' strips cut at that height give fewer tasks than the
+// device holds at once (about four four-wave workgroups, or eight single
+// waves, per compute unit), as with a few small members or one job of a
+// lightly loaded serving pool -- the height that gives about that many
+// tasks, at least 4(T-1) rows (the pipeline repeats 2(T-1) start-up rows
+// per segment), as long as the tile table holds them.
+int table_seg_rows(const lbm_pool *P)
+{
+    const lbm_pool_shape &sh = P->shape;
+    if (sh.steps_per_launch < 2) return sh.seg_rows;
+    int64_t strip_rows = 0, tasks = 0, onestep = 0;
+    for (const Slot &sl : P->slots) {
+        if (!sl.lat || sl.t_done >= sl.t_target) continue;
+        const int n = strips_of(sh, sl.lat);
+        strip_rows += (int64_t)n * sl.lat->v.ny;
+        tasks += (int64_t)n * segments_of(sh.seg_rows, sl.lat);
+        onestep += onestep_tiles_of(sh, sl.lat);
+    }
+    const int64_t fill = (int64_t)lbm::device_cus() * (wg_table(sh) ? 4 : 8);
+    if (tasks >= fill) return sh.seg_rows;
+    const int low = std::max(8, 4 * (sh.steps_per_launch - 1));
+    const int seg = (int)std::max<int64_t>(low, std::min<int64_t>(sh.seg_rows, strip_rows / fill));
+    int64_t need = onestep;
+    for (const Slot &sl : P->slots)
+        if (sl.lat && sl.t_done < sl.t_target) need += (int64_t)strips_of(sh, sl.lat) * segments_of(seg, sl.lat);
+    return need <= P->max_tiles ? seg : sh.seg_rows;
 }
 
 void drop_graphs(lbm_pool *P)
@@ -212,6 +250,7 @@ lbm_status upload(lbm_pool *P)
             load[c][best] -= e.first;
         }
     }
+    const int seg_rows = table_seg_rows(P);
     struct T { int range; int64_t cells; lbm::PoolTile t; };
     std::vector<T> all, tasks, twos;
     for (int i = 0; i < P->max_members; ++i) {
@@ -255,7 +294,7 @@ lbm_status upload(lbm_pool *P)
             // four-wave (or one-wave) strips, then a two-wave one
             const bool wg = wg_table(P->shape);
             const WgStrips g = wg ? wg_strips(P->shape, L) : WgStrips{0, 0, 0};
-            const int w = task_cols(P->shape, L), k = segments_of(P->shape, L);
+            const int w = task_cols(P->shape, L), k = segments_of(seg_rows, L);
             const int nfull = wg ? g.n4 : (L->v.nx + w - 1) / w;
             for (int sg = 0; sg < k; ++sg) {
                 const int y0 = (int)((int64_t)L->v.ny * sg / k), y1 = (int)((int64_t)L->v.ny * (sg + 1) / k);

@@ -190,6 +190,16 @@ def order_queue(queue, policy, now):
     raise ValueError(f"policy must be 'aged', 'sjf' or 'fifo', not {policy!r}")
 
 
+_SIDE_STREAMS = {}
+
+
+def _side_stream(device):
+    key = torch.device(device).index or 0
+    if key not in _SIDE_STREAMS:
+        _SIDE_STREAMS[key] = torch.cuda.Stream(torch.device(device))
+    return _SIDE_STREAMS[key]
+
+
 class Server:
     """policy: "aged" (default) admits the queued job with the least work
     (cells x steps) first unless a job has aged (see order_queue), "sjf" the
@@ -221,8 +231,12 @@ class Server:
         self.rejected = []
         # Jobs are initialised and read back on a side stream: a finished
         # job's readback then waits for its own last chunk only, not for the
-        # chunks enqueued after it on the pool's stream.
-        self.side = torch.cuda.Stream(self.device)
+        # chunks enqueued after it on the pool's stream.  One such stream per
+        # device serves every server of the process: torch's caching
+        # allocator reuses a freed block only on the stream it was allocated
+        # on, so a stream per server would keep every earlier server's job
+        # memory reserved.
+        self.side = _side_stream(self.device)
 
     def _chunk_steps(self, active_bytes_per_step):
         # about chunk_ms of device work; short steps are bounded below by launch cost
