@@ -184,7 +184,8 @@ int tiles_of(const lbm_pool_shape &sh, const lbm_lattice *L) { return onestep_ti
 // waves, per compute unit), as with a few small members or one job of a
 // lightly loaded serving pool -- the height that gives about that many
 // tasks, at least 4(T-1) rows (the pipeline repeats 2(T-1) start-up rows
-// per segment), as long as the tile table holds them.
+// per segment) and never above seg_rows, as long as the tile table holds
+// them.
 int table_seg_rows(const lbm_pool *P)
 {
     const lbm_pool_shape &sh = P->shape;
@@ -199,7 +200,7 @@ int table_seg_rows(const lbm_pool *P)
     }
     const int64_t fill = (int64_t)lbm::device_cus() * (wg_table(sh) ? 4 : 8);
     if (tasks >= fill) return sh.seg_rows;
-    const int low = std::max(8, 4 * (sh.steps_per_launch - 1));
+    const int low = std::min(sh.seg_rows, std::max(8, 4 * (sh.steps_per_launch - 1)));
     const int seg = (int)std::max<int64_t>(low, std::min<int64_t>(sh.seg_rows, strip_rows / fill));
     int64_t need = onestep;
     for (const Slot &sl : P->slots)
