@@ -235,3 +235,22 @@ def test_shared_halo_table_member_parity_with_oracle_fp64():
     f = lat.populations().cpu().numpy()
     assert np.max(np.abs(f - ref)) <= 1e-12 * np.max(np.abs(ref))
     pool.close()
+
+
+def test_shared_halo_shapes_need_four_waves_and_no_internal_bits():
+    # flag 32 tables run four-wave workgroups; bit 6 (two-wave workgroups)
+    # is internal to the pool's own launches, not a shape flag
+    from paper_1107_4543_amd import _lib
+    from paper_1107_4543_amd.pool import Pool
+    pool = Pool(max_members=2, max_tiles=256)
+    for waves in (1, 2, 3):
+        with pytest.raises(_lib.LbmError) as e:
+            pool.set_shape(steps_per_launch=7, seg_rows=64, waves=waves, flags=32)
+        assert e.value.status == _lib.LBM_E_INVAL
+    for flags in (64, 96, 98):
+        with pytest.raises(_lib.LbmError) as e:
+            pool.set_shape(steps_per_launch=7, seg_rows=64, waves=4, flags=flags)
+        assert e.value.status == _lib.LBM_E_INVAL
+    pool.set_shape(steps_per_launch=7, seg_rows=64, waves=4, flags=34)
+    assert pool.shape["flags"] == 34
+    pool.close()
