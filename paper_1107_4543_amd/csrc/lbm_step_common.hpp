@@ -94,6 +94,18 @@ __device__ __forceinline__ int remap_xcd(int bid, int nb)
     return xcd * per + (xcd < rem ? xcd : rem) + local;
 }
 
+// Task of workgroup b among n tasks that keeps their order (longest first)
+// chunk by chunk but gives each XCD (workgroups b, b + 8, ... run on XCD b
+// mod 8) four consecutive tasks of every 32: adjacent strips of one lattice
+// then load their shared halo columns and edge cache lines through the same
+// L2.  The last partial chunk keeps the plain order.
+__device__ __forceinline__ int xcd_group(int b, int n)
+{
+    const int c = b >> 5;
+    if ((c + 1) << 5 > n) return b;
+    return (c << 5) + ((b & 7) << 2) + ((b & 31) >> 3);
+}
+
 // Collide one cell held as widened stored values w (in place).  16-bit
 // storage is collided in its scaled units (see collide_increment).  The
 // last operation before a value is rounded to its storage type is the add
@@ -780,7 +792,8 @@ k_pool_multi(const PoolHeader *__restrict__ hdr, const PoolMember *__restrict__ 
         __shared__ typename Store<S>::wide wgx[wg_exchange_values<T, FLAGS>()];
         // the exchange rows hold the columns of exactly this many waves
         if ((int)blockDim.y != (TWO ? 2 : kWgMaxWaves)) return;
-        for (int ti = begin + (int)blockIdx.x; ti < end; ti += (int)gridDim.x) {
+        for (int v = (int)blockIdx.x; v < end - begin; v += (int)gridDim.x) {
+            const int ti = begin + xcd_group(v, end - begin);
             const PoolTile tile = tiles[ti];             // workgroup-uniform
             const PoolMember *m = mem + tile.member;
             if ((int64_t)(j + 1) * T > m->t_target - m->t_done) continue;
