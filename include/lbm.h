@@ -101,13 +101,13 @@ typedef struct lbm_desc {
 typedef struct lbm_lattice lbm_lattice;
 
 /* Launch shape of the fused step kernel (chosen by lbm_tune or set by hand;
- * a new lattice of at least 2^22 cells starts with a several-steps shape
- * by storage type: FP32 {13, 64, 4, R, 1, 32}, FP16 {12, 64, 4, R, 1, 34},
- * BF16 {12, 64, 4, R, 1, 40}, FP64 {13, 64, 4, R, 1, 32} (workgroup-shared
- * halo, R chosen from the lattice size so that three (FP32), four (FP16,
- * BF16) or two (FP64) workgroups per compute unit cover the lattice in one
- * round: 92, 69, 69, 137 rows on 4096^2); a smaller one with
- * {0, 64, 4, 1, 1, 0}).
+ * a new lattice of at least 2^19 cells (FP32, FP64 storage) or 2^21 cells
+ * (FP16, BF16) starts with a several-steps shape by storage type: FP32
+ * {13, 64, 4, R, 1, 32}, FP16 {12, 64, 4, R, 1, 34}, BF16 {12, 64, 4, R, 1,
+ * 40}, FP64 {13, 64, 4, R, 1, 32} (workgroup-shared halo, R chosen from the
+ * lattice size so that three (FP32), four (FP16, BF16) or two (FP64)
+ * workgroups per compute unit cover the lattice in one round, at least 8:
+ * 92, 69, 69, 137 rows on 4096^2); a smaller one with {0, 64, 4, 1, 1, 0}).
  *   variant   0 = one cell per lane (nine direct loads),
  *             1, 2, 3 = 2, 4, 8 consecutive cells per lane (aligned vector
  *             loads, x-shift by cross-lane exchange; needs nx % 2^variant == 0

@@ -134,19 +134,24 @@ int wg_rows(const View &v, int T, int waves, int per_cu)
     return std::max(1, std::min(4096, (v.ny + segs - 1) / segs));
 }
 
-// Large lattices (>= 2^22 cells): several steps per launch with the shape
-// measured fastest for the storage type on the 4096^2 wave workload: for
-// 32- and 16-bit storage the workgroup-shared halo with four waves per
-// workgroup -- FP32: T = 7, loads not ahead (flags 32), segments for three
-// workgroups per compute unit (92 rows on 4096^2); FP16: T = 6, one row
-// ahead (34), BF16: T = 6, two rows ahead (40), four per compute unit (69
-// rows); FP64: T = 7, loads not ahead (32),
-// two per compute unit (137 rows; a wave then holds about 250 registers).
-// Smaller lattices offer too few strip segments to keep the GPU busy through
-// the pipeline and keep the one-step shape.
+// Several steps per launch with the shape measured fastest for the storage
+// type on the 4096^2 wave workload: for 32- and 16-bit storage the
+// workgroup-shared halo with four waves per workgroup -- FP32: T = 7, loads
+// not ahead (flags 32), segments for three workgroups per compute unit (92
+// rows on 4096^2); FP16: T = 6, one row ahead (34), BF16: T = 6, two rows
+// ahead (40), four per compute unit (69 rows); FP64: T = 7, loads not ahead
+// (32), two per compute unit (137 rows; a wave then holds about 250
+// registers).  This from 2^19 cells for FP32 and FP64 storage and from 2^21
+// for 16-bit storage (whose one-step kernel moves half the bytes and stays
+// competitive longer), with segments of at least 8 rows: on small lattices
+// the segments that give that workgroup count are short and the pipeline's
+// start-up rows weigh more, yet the several-steps kernel measured 1.3-2.7x
+// the one-step kernel from 640^2 to 2048 x 1024 (FP32, FP64) and from 1280^2
+// (16-bit).  Smaller lattices keep the one-step shape.
 lbm_launch default_launch(const View &v)
 {
-    if ((int64_t)v.nx * v.ny < ((int64_t)1 << 22)) return default_single(v);
+    const bool half = v.storage == LBM_STORE_F16 || v.storage == LBM_STORE_BF16;
+    if ((int64_t)v.nx * v.ny < ((int64_t)1 << (half ? 21 : 19))) return default_single(v);
     lbm_launch c{};
     c.block_x = 64;
     c.xcd_remap = 1;
@@ -156,6 +161,7 @@ lbm_launch default_launch(const View &v)
     case LBM_STORE_BF16: c.variant = 12; c.block_y = 4; c.flags = 40; c.rows = wg_rows(v, 6, 4, 4); break;
     default: c.variant = 13; c.block_y = 4; c.flags = 32; c.rows = wg_rows(v, 7, 4, 2); break;
     }
+    c.rows = std::max(c.rows, 8);
     return c;
 }
 

@@ -179,12 +179,14 @@ int onestep_tiles_of(const lbm_pool_shape &sh, const lbm_lattice *L)
 int tiles_of(const lbm_pool_shape &sh, const lbm_lattice *L) { return onestep_tiles_of(sh, L) + tasks_of(sh, L); }
 
 // Segment height of a pool's table: the shape's seg_rows, or -- when the
-// unfinished members' strips cut at that height give fewer tasks than the
-// device holds at once (about four four-wave workgroups, or eight single
-// waves, per compute unit), as with a few small members or one job of a
+// unfinished members' strips cut at that height give fewer tasks than fill
+// the device once (three four-wave workgroups per compute unit, the count a
+// single lattice's default measured best with, or eight single waves), as
+// with a few small members or one job of a
 // lightly loaded serving pool -- the height that gives about that many
-// tasks, at least 4(T-1) rows (the pipeline repeats 2(T-1) start-up rows
-// per segment) and never above seg_rows, as long as the tile table holds
+// tasks, at least 8 rows (as a single lattice's default shape: the pipeline
+// then repeats its 2(T-1) start-up rows often, yet a full device still
+// measured faster) and never above seg_rows, as long as the tile table holds
 // them.
 int table_seg_rows(const lbm_pool *P)
 {
@@ -198,9 +200,9 @@ int table_seg_rows(const lbm_pool *P)
         tasks += (int64_t)n * segments_of(sh.seg_rows, sl.lat);
         onestep += onestep_tiles_of(sh, sl.lat);
     }
-    const int64_t fill = (int64_t)lbm::device_cus() * (wg_table(sh) ? 4 : 8);
+    const int64_t fill = (int64_t)lbm::device_cus() * (wg_table(sh) ? 3 : 8);
     if (tasks >= fill) return sh.seg_rows;
-    const int low = std::min(sh.seg_rows, std::max(8, 4 * (sh.steps_per_launch - 1)));
+    const int low = std::min(sh.seg_rows, 8);
     const int seg = (int)std::max<int64_t>(low, std::min<int64_t>(sh.seg_rows, strip_rows / fill));
     int64_t need = onestep;
     for (const Slot &sl : P->slots)

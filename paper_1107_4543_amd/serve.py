@@ -42,7 +42,6 @@ from .pool import Pool
 from . import stability
 
 STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
-HBM_GBPS_ESTIMATE = 6000.0      # for sizing chunks only
 
 
 @dataclass
@@ -209,13 +208,14 @@ class Server:
     what each JobResult carries besides the diagnostics (None, "digest",
     "state" or "fields")."""
 
-    def __init__(self, hbm_budget_bytes, max_members=256, max_tiles=1 << 20, chunk_ms=10.0,
+    def __init__(self, hbm_budget_bytes, max_members=256, max_tiles=1 << 20, chunk_ms=5.0,
                  device="cuda:0", screen=False, tune=False, policy="aged", max_active_cells=1 << 25,
                  tile_cells=512, keep=None):
         self.device = torch.device(device)
         self.budget = int(hbm_budget_bytes)
         self.pool = Pool(max_members=max_members, max_tiles=max_tiles, device=self.device)
         self.pool.set_shape(tile_cells=tile_cells, block=512, grid=4096, graph_steps=256)
+        self.steps_per_launch = self.pool.shape["steps_per_launch"]
         self.max_members = max_members
         self.chunk_ms = chunk_ms
         if policy not in ("aged", "sjf", "fifo"):
@@ -238,10 +238,13 @@ class Server:
         # memory reserved.
         self.side = _side_stream(self.device)
 
-    def _chunk_steps(self, active_bytes_per_step):
-        # about chunk_ms of device work; short steps are bounded below by launch cost
-        est_ms = max(active_bytes_per_step / (HBM_GBPS_ESTIMATE * 1e6), 0.004)
-        return max(1, min(1024, int(self.chunk_ms / est_ms)))
+    def _chunk_steps(self, active_cells):
+        # about chunk_ms of device work at the pool's update rate (short steps
+        # are bounded below by launch cost), in whole T-step launches: a count
+        # that is not a multiple of T ends every chunk in one-step launches
+        est_ms = max(active_cells / SERVICE_LUPS_ESTIMATE * 1e3, 0.004)
+        n = max(1, min(1024, int(self.chunk_ms / est_ms)))
+        return n - n % self.steps_per_launch if n >= self.steps_per_launch else n
 
     def run(self, trace) -> List[JobResult]:
         pending = collections.deque(sorted(trace, key=lambda s: s.arrival))
@@ -283,8 +286,7 @@ class Server:
                 self.peak_members = max(self.peak_members, len(active))
             running = [a for a in active.values() if self.pool.remaining(a[3]) > 0]
             if running:
-                bps = sum(72 * a[0].nx * a[0].ny * STORE_BYTES[a[0].storage] / 4 for a in running)
-                self.pool.step(self._chunk_steps(bps))
+                self.pool.step(self._chunk_steps(sum(a[0].nx * a[0].ny for a in running)))
                 ev = torch.cuda.Event()
                 ev.record(stream)
                 inflight.append(ev)

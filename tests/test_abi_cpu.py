@@ -193,3 +193,24 @@ def test_step_launch_counts_follow_the_remainder_rule():
 def test_status_strings():
     for s in (0, -1, -2, -3, -4, -5, 42):
         assert isinstance(_lib.lbm_status_string(s), str) and _lib.lbm_status_string(s)
+
+
+def test_default_shapes_by_size_and_storage():
+    # several steps per launch from 2^19 cells (FP32, FP64) or 2^21 cells
+    # (FP16, BF16), with segments of at least 8 rows; one step below
+    fake = 1 << 32
+    cases = [("f32", 512, 512, 0), ("f32", 1024, 512, 13), ("f32", 1024, 1024, 13), ("f64", 1024, 1024, 13),
+             ("f16", 1024, 1024, 0), ("bf16", 2048, 512, 0), ("f16", 2048, 1024, 12), ("bf16", 4096, 4096, 12),
+             ("f32", 4096, 4096, 13)]
+    for storage, nx, ny, variant in cases:
+        d = desc(nx=nx, ny=ny)
+        d.storage = _lib.STORAGE[storage]
+        d.compute = _lib.LBM_COMPUTE_F64 if storage == "f64" else _lib.LBM_COMPUTE_F32
+        h = _lib.lbm_create(d, fake, _lib.lbm_workspace_bytes(d), 0)
+        try:
+            c = _lib.lbm_get_launch(h).as_dict()
+            assert c["variant"] == variant, (storage, nx, ny, c)
+            if variant:
+                assert c["block_y"] == 4 and c["flags"] & 32 and c["rows"] >= 8, c
+        finally:
+            _lib.lbm_destroy(h)
