@@ -205,3 +205,30 @@ def test_projection_matches_numpy_fourier_sum():
         got = np_(lat.project(mx, my))
         got = got[0::2] + 1j * got[1::2]
         assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want)) + tol_abs, (mx, my)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_mid_size_default_is_several_steps_and_matches_the_oracle(storage):
+    # 1100 x 480 = 528,000 cells (at least 2^19): the lattice starts with the
+    # several-steps shared-halo shape with short segments (at least 8 rows),
+    # whose last strip is partial; 45 steps are six 7-step passes and one
+    # 3-step pass.  Two pulses, one across the periodic seams in x and y.
+    nx, ny, steps, A = 1100, 480, 45, 1e-3
+    s = t5a_rates()
+    rho, ux, uy = lbm_inputs.gaussian_pulse(nx, ny, A, 9.0, center=(300.4, 210.7), u0=(0.05, 0.0))
+    rho2, _, _ = lbm_inputs.gaussian_pulse(nx, ny, 0.5 * A, 6.0, center=(1096.2, 2.5))
+    rho = rho + (rho2 - 1.0)
+    lat = lattice(nx, ny, s, storage=storage, u0=(0.05, 0.0))
+    c = lat.launch
+    assert c["variant"] == 13 and c["flags"] & 32 and c["rows"] >= 8, c
+    lat.init(rho, ux, uy).step(steps)
+    ref = oracle.run(oracle.init(rho, ux, uy), s, steps)
+    if storage == "f64":
+        check_f64(lat, ref)
+        return
+    rr, ur, vr = oracle.moments(ref)
+    r, u, v = (np_(a) for a in lat.moments())
+    assert np.max(np.abs(r - rr)) <= 1e-5 * A
+    Au = max(np.max(np.abs(ux - 0.05)), np.max(np.abs(uy)), np.max(np.abs(ur - 0.05)))
+    assert np.max(np.abs(u - ur)) <= 1e-5 * Au
+    assert np.max(np.abs(v - vr)) <= 1e-5 * Au
