@@ -20,7 +20,11 @@ collision's 70 (FP32, FP64) or 71 (16-bit storage) algorithmic operations
 per cell and step against the non-packed issue peak), with the HBM figures
 beside it -- measured HBM traffic from the committed rocprofv3 counter
 summary when it matches the current kernel source, and the FP64 CPU oracle
-timed on a bounded sample of the same workload on the host cores.
+timed on a bounded sample of the same workload on the host cores.  Beside the
+single lattice the line carries the batched workload (256 lattices advanced
+together by the pool kernel against one at a time) and one served trace
+(Poisson arrivals of simulation jobs, continuous batching against one job at
+a time: latency percentiles, aggregate MLUPS and per-job digest equality).
 """
 import argparse
 import hashlib
@@ -401,6 +405,49 @@ def bench_batch256(args):
     }
 
 
+def serve_warmup(budget):
+    """Untimed warm-up of the serving modes: the first use of each kernel,
+    pool graph and allocation size in the process is not charged to the
+    first measured trace."""
+    import lbm_inputs
+    from paper_1107_4543_amd import stability
+    from paper_1107_4543_amd.serve import Server, run_plain
+    warm = lbm_inputs.serving_trace(99, 1000.0, 24, accept=stability.stable)
+    for policy in ("aged", "fifo"):
+        srv = Server(budget, max_members=256, policy=policy, keep="digest")
+        srv.run(warm)
+        srv.close()
+    run_plain(warm, keep="digest")
+
+
+def serve_rate(seed, rate, jobs, budget, policies):
+    """One Poisson trace (seed, rate in jobs/s, jobs) served under each
+    admission policy and run one job at a time; every job's final raw state
+    is compared between the modes through its on-device digest.  The first
+    policy is the one reported as "served"."""
+    import lbm_inputs
+    from paper_1107_4543_amd import stability
+    from paper_1107_4543_amd.serve import Server, run_plain, summarize
+    trace = lbm_inputs.serving_trace(seed, rate, jobs, accept=stability.stable)
+    modes, peak = {}, {}
+    for policy in policies:
+        srv = Server(budget, max_members=256, policy=policy, keep="digest")
+        modes[policy] = srv.run(trace)
+        srv.close()
+        peak[policy] = (srv.peak_members, round(srv.peak_used / 1e9, 2), len(srv.rejected))
+    plain = run_plain(trace, keep="digest")
+    pd = {r.tag: r.digest for r in plain}
+    mismatched = sorted({r.tag for rs in modes.values() for r in rs if r.digest != pd.get(r.tag)})
+    first = policies[0]
+    row = {"rate_jobs_per_s": rate, "jobs": len(trace), "seed": seed, "served": summarize(modes[first]),
+           **{"served_" + p: summarize(modes[p]) for p in policies[1:]},
+           "plain": summarize(plain),
+           "equal_results": not mismatched and all(len(rs) == len(trace) for rs in modes.values()),
+           "jobs_compared": sum(len(rs) for rs in modes.values()), "mismatched_jobs": mismatched,
+           "rejected": peak[first][2], "peak_members": peak[first][0], "peak_budget_gb": peak[first][1]}
+    return row
+
+
 def bench_serve(args):
     """Poisson arrivals of simulation jobs (square side log-uniform in
     [128, 4096], steps uniform in [200, 5000], FP32 or FP16 storage 50/50,
@@ -411,37 +458,11 @@ def bench_serve(args):
     lattice's default launches.  Latency = arrival to result on the host.
     Every job's final raw state is compared between the modes through an
     on-device digest of its stored values."""
-    import lbm_inputs
-    from paper_1107_4543_amd import stability
-    from paper_1107_4543_amd.serve import Server, run_plain, summarize
     out = []
     budget = int(args.budget_gb * 1e9)
-    # untimed warm-up: the first use of each kernel, pool graph and allocation
-    # size in the process is not charged to the first rate's first mode
-    warm = lbm_inputs.serving_trace(99, 1000.0, 24, accept=stability.stable)
-    for policy in ("aged", "fifo"):
-        srv = Server(budget, max_members=256, policy=policy, keep="digest")
-        srv.run(warm)
-        srv.close()
-    run_plain(warm, keep="digest")
+    serve_warmup(budget)
     for i, rate in enumerate(float(r) for r in args.rates.split(",")):
-        trace = lbm_inputs.serving_trace(100 + i, rate, args.jobs, accept=stability.stable)
-        modes = {}
-        peak = {}
-        for policy in ("aged", "sjf", "fifo"):
-            srv = Server(budget, max_members=256, policy=policy, keep="digest")
-            modes[policy] = srv.run(trace)
-            srv.close()
-            peak[policy] = (srv.peak_members, round(srv.peak_used / 1e9, 2), len(srv.rejected))
-        plain = run_plain(trace, keep="digest")
-        pd = {r.tag: r.digest for r in plain}
-        mismatched = sorted({r.tag for rs in modes.values() for r in rs if r.digest != pd.get(r.tag)})
-        row = {"rate_jobs_per_s": rate, "jobs": len(trace), "served": summarize(modes["aged"]),
-               "served_sjf": summarize(modes["sjf"]), "served_fifo": summarize(modes["fifo"]),
-               "plain": summarize(plain),
-               "equal_results": not mismatched and all(len(rs) == len(trace) for rs in modes.values()),
-               "jobs_compared": sum(len(rs) for rs in modes.values()), "mismatched_jobs": mismatched,
-               "rejected": peak["aged"][2], "peak_members": peak["aged"][0], "peak_budget_gb": peak["aged"][1]}
+        row = serve_rate(100 + i, rate, args.jobs, budget, ("aged", "sjf", "fifo"))
         out.append(row)
         print(json.dumps({"progress": row}), file=sys.stderr, flush=True)
     top = out[-1]["served"]
@@ -555,6 +576,10 @@ def main():
                     help="seconds of one-thread oracle work (0 = skip)")
     ap.add_argument("--batched-steps", type=int, default=500,
                     help="default workload: steps of the batched 256-lattice run reported beside it (0 = skip)")
+    ap.add_argument("--served-jobs", type=int, default=100,
+                    help="default workload: jobs of the served-vs-plain trace reported beside it (0 = skip)")
+    ap.add_argument("--served-rate", type=float, default=1000.0,
+                    help="default workload: arrival rate (jobs/s) of that trace")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -689,6 +714,13 @@ def main():
                                "seed": r["seed"], "pool_shape": r["shape"],
                                "job_steps": lbm_inputs.WORKLOADS["batch256"]["steps"]},
                               **batch_summary(r, args.batched_steps))
+    if args.served_jobs > 0:
+        # one Poisson trace served with continuous batching (aged shortest job
+        # first, the server's default) and one job at a time, same jobs
+        budget = int(args.budget_gb * 1e9)
+        serve_warmup(budget)
+        row = serve_rate(100, args.served_rate, args.served_jobs, budget, ("aged",))
+        out["serving"] = dict({"workload": "serve", "budget_gb": args.budget_gb}, **row)
     if args.cpu_budget > 0:
         out["cpu_baseline"] = cpu_baseline(rates, fields1, cfg["nx"], cfg["ny"], w["u0x"], args.cpu_budget,
                                            args.cpu_budget_1t)

@@ -1,7 +1,8 @@
 """The JSON line bench.py prints for the 4096^2 wave workload: the fields a
-measurement harness reads, and a roofline that follows from the line's own
+measurement harness reads, a roofline that follows from the line's own
 numbers and whose bound matches the launch shape (vector ALU for several
-steps per launch, HBM for one step)."""
+steps per launch, HBM for one step), and the batched and served objects the
+default line carries beside it."""
 import json
 import os
 import subprocess
@@ -18,7 +19,7 @@ ALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 
 def run_bench(steps, *extra):
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", str(steps), "--warmup", "7",
-                        "--cpu-budget", "0", "--batched-steps", "0", *extra],
+                        "--cpu-budget", "0", "--batched-steps", "0", "--served-jobs", "0", *extra],
                        capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stderr[-2000:]
     return json.loads(r.stdout.strip().splitlines()[-1])
@@ -32,6 +33,7 @@ def test_bench_line_for_the_several_steps_default(steps):
         assert k in d, k
     assert d["n_gpus"] == 1 and d["steps"] == steps and d["unit"] == "MLUPS" and d["value"] > 0
     assert d["config"]["workload"] == "waves4096" and "cpu_baseline" not in d and "batched" not in d
+    assert "serving" not in d
     r = d["roofline"]
     T = r["steps_per_launch"]
     assert r["bound"] == "alu" and T > 1
@@ -64,3 +66,19 @@ def test_bench_line_for_one_step_per_launch():
     assert r["bound"] == "hbm" and r["steps_per_launch"] == 1 and r["launches"] == 30
     assert abs(r["achieved"] - r["algorithmic_bytes_per_launch"] / (r["avg_launch_us"] * 1e-6) / 1e9) < 0.5
     assert abs(r["achieved"] - r["one_pass_equiv"]["achieved"]) < 0.01 * r["achieved"]
+
+
+def test_bench_line_carries_the_batched_and_served_workloads():
+    # last argument wins: the batched run and a short served trace are on
+    d = run_bench(14, "--batched-steps", "14", "--served-jobs", "24")
+    b = d["batched"]
+    assert b["workload"] == "batch256" and b["lattices"] == 256 and b["value"] > 0
+    s = d["serving"]
+    assert s["workload"] == "serve" and s["jobs"] == 24 and s["rate_jobs_per_s"] == 1000.0
+    assert s["served"]["jobs"] == 24 and s["plain"]["jobs"] == 24
+    # every served job's final state equals its plain run's (on-device digests)
+    assert s["equal_results"] and s["jobs_compared"] == 24 and s["mismatched_jobs"] == []
+    assert s["rejected"] == 0 and s["served"]["nonfinite_jobs"] == 0
+    for mode in ("served", "plain"):
+        m = s[mode]
+        assert 0 < m["p50_s"] <= m["p99_s"] <= m["max_s"] and m["aggregate_mlups"] > 0
