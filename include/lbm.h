@@ -101,8 +101,8 @@ typedef struct lbm_desc {
 typedef struct lbm_lattice lbm_lattice;
 
 /* Launch shape of the fused step kernel (chosen by lbm_tune or set by hand;
- * a new lattice of at least 2^19 cells (FP32, FP64 storage) or 2^21 cells
- * (FP16, BF16) starts with a several-steps shape by storage type: FP32
+ * a new lattice of at least 2^19 cells starts with a several-steps shape by
+ * storage type: FP32
  * {13, 64, 4, R, 1, 32}, FP16 {12, 64, 4, R, 1, 34}, BF16 {12, 64, 4, R, 1,
  * 40}, FP64 {13, 64, 4, R, 1, 32} (workgroup-shared halo, R chosen from the
  * lattice size so that three (FP32), four (FP16, BF16) or two (FP64)

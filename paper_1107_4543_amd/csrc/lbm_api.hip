@@ -141,17 +141,15 @@ int wg_rows(const View &v, int T, int waves, int per_cu)
 // rows on 4096^2); FP16: T = 6, one row ahead (34), BF16: T = 6, two rows
 // ahead (40), four per compute unit (69 rows); FP64: T = 7, loads not ahead
 // (32), two per compute unit (137 rows; a wave then holds about 250
-// registers).  This from 2^19 cells for FP32 and FP64 storage and from 2^21
-// for 16-bit storage (whose one-step kernel moves half the bytes and stays
-// competitive longer), with segments of at least 8 rows: on small lattices
-// the segments that give that workgroup count are short and the pipeline's
-// start-up rows weigh more, yet the several-steps kernel measured 1.3-2.7x
-// the one-step kernel from 640^2 to 2048 x 1024 (FP32, FP64) and from 1280^2
-// (16-bit).  Smaller lattices keep the one-step shape.
+// registers).  This from 2^19 cells, with segments of at least 8 rows: on
+// small lattices the segments that give that workgroup count are short and
+// the pipeline's start-up rows weigh more, yet the several-steps kernel
+// measured 1.3-2.7x the one-step kernel from 640^2 to 2048 x 1024 (FP32,
+// FP64), and for 16-bit storage 1.2x (FP16) and even (BF16) at 768^2, 1.4-1.5x
+// at 1024^2 and 2x at 1448^2.  Smaller lattices keep the one-step shape.
 lbm_launch default_launch(const View &v)
 {
-    const bool half = v.storage == LBM_STORE_F16 || v.storage == LBM_STORE_BF16;
-    if ((int64_t)v.nx * v.ny < ((int64_t)1 << (half ? 21 : 19))) return default_single(v);
+    if ((int64_t)v.nx * v.ny < ((int64_t)1 << 19)) return default_single(v);
     lbm_launch c{};
     c.block_x = 64;
     c.xcd_remap = 1;

@@ -18,6 +18,11 @@ a number of steps.  ``Server.run`` replays a trace of jobs in real time:
 * the pool advances all admitted jobs together, one chunk of steps at a time
   (persistent batched launches, recorded step loop), with at most two chunks
   in flight so that admissions and completions are handled between chunks;
+  a job admitted to an empty server with nothing queued behind it advances
+  alone with its own lattice's default launches (``solo``), and joins the
+  pool with its remaining steps as soon as a second job is admitted (every
+  launch shape gives the same values, so the result does not depend on
+  when, or whether, it joins);
 * a job leaves the pool after exactly its own number of steps; its result
   is read and its memory returned to the budget: the FP64 mass/momentum
   diagnostics, and (``keep``) a digest of its raw final state, or the raw
@@ -206,11 +211,15 @@ class Server:
     at once (enough to fill the GPU; more only stretches every job's
     latency), in addition to the HBM budget and the member slots.  keep:
     what each JobResult carries besides the diagnostics (None, "digest",
-    "state" or "fields")."""
+    "state" or "fields").  solo: a job admitted to an empty server with
+    nothing queued advances with its lattice's own default launches until a
+    second job is admitted (the pool's batched kernels pay a table lookup
+    and a launch shape shared by every member; one job alone runs faster
+    with the shape chosen for its lattice)."""
 
     def __init__(self, hbm_budget_bytes, max_members=256, max_tiles=1 << 20, chunk_ms=5.0,
                  device="cuda:0", screen=False, tune=False, policy="aged", max_active_cells=1 << 25,
-                 tile_cells=512, keep=None):
+                 tile_cells=512, keep=None, solo=True):
         self.device = torch.device(device)
         self.budget = int(hbm_budget_bytes)
         self.pool = Pool(max_members=max_members, max_tiles=max_tiles, device=self.device)
@@ -223,12 +232,15 @@ class Server:
         self.policy = policy
         self.keep = keep
         self.max_active_cells = max_active_cells
+        self.solo = solo
         self.screen = screen
         self.tune = tune
         self.used = 0
         self.peak_used = 0
         self.peak_members = 0
         self.rejected = []
+        self.solo_started = 0                        # jobs that began alone
+        self.solo_joined = 0                         # ... and joined the pool with steps left
         # Jobs are initialised and read back on a side stream: a finished
         # job's readback then waits for its own last chunk only, not for the
         # chunks enqueued after it on the pool's stream.  One such stream per
@@ -242,9 +254,12 @@ class Server:
         # about chunk_ms of device work at the pool's update rate (short steps
         # are bounded below by launch cost), in whole T-step launches: a count
         # that is not a multiple of T ends every chunk in one-step launches
-        est_ms = max(active_cells / SERVICE_LUPS_ESTIMATE * 1e3, 0.004)
+        return self._chunk(active_cells, self.steps_per_launch)
+
+    def _chunk(self, cells, spl):
+        est_ms = max(cells / SERVICE_LUPS_ESTIMATE * 1e3, 0.004)
         n = max(1, min(1024, int(self.chunk_ms / est_ms)))
-        return n - n % self.steps_per_launch if n >= self.steps_per_launch else n
+        return n - n % spl if n >= spl else n
 
     def run(self, trace) -> List[JobResult]:
         pending = collections.deque(sorted(trace, key=lambda s: s.arrival))
@@ -253,6 +268,9 @@ class Server:
         inflight = collections.deque()
         results = []
         stream = self.pool.stream
+        # the job advancing alone outside the pool: [lattice, steps not yet
+        # enqueued, event after its last step (once all are enqueued)]
+        solo = None
         t0 = time.perf_counter()
         while pending or queue or active:
             now = time.perf_counter() - t0
@@ -272,27 +290,60 @@ class Server:
                         or (active and active_cells + spec.nx * spec.ny > self.max_active_cells)):
                     break
                 lat = _new_lattice(spec, self.device, self.side)
-                try:
-                    self.pool.add(lat, spec.steps)
-                except _lib.LbmError as e:
-                    if e.status != _lib.LBM_E_NOMEM or not active:
-                        raise
-                    lat.close()                      # tile table full: retry when a job leaves
-                    break
+                if self.solo and not active and len(queue) == 1:
+                    solo = [lat, spec.steps, None]
+                    self.solo_started += 1
+                else:
+                    if solo is not None and solo[1] > 0:
+                        # a second job: the lone one joins the pool with the
+                        # steps it has left (the pool waits for its queued ones)
+                        self.pool.add(solo[0], solo[1])
+                        solo = None
+                        self.solo_joined += 1
+                    try:
+                        self.pool.add(lat, spec.steps)
+                    except _lib.LbmError as e:
+                        if e.status != _lib.LBM_E_NOMEM or not active:
+                            raise
+                        lat.close()                  # tile table full: retry when a job leaves
+                        break
                 queue.popleft()
                 active[id(lat)] = (spec, time.perf_counter() - t0, need, lat)
                 self.used += need
                 self.peak_used = max(self.peak_used, self.used)
                 self.peak_members = max(self.peak_members, len(active))
-            running = [a for a in active.values() if self.pool.remaining(a[3]) > 0]
+            solo_lat = solo[0] if solo is not None else None
+            pooled = [a for a in active.values() if a[3] is not solo_lat]
+            running = [a for a in pooled if self.pool.remaining(a[3]) > 0]
             if running:
                 self.pool.step(self._chunk_steps(sum(a[0].nx * a[0].ny for a in running)))
                 ev = torch.cuda.Event()
                 ev.record(stream)
                 inflight.append(ev)
-                while len(inflight) > 2:
-                    inflight.popleft().synchronize()
-            finished = self.pool.poll(wait=not running and bool(active))
+            if solo is not None and solo[2] is None:
+                lat = solo[0]
+                n = min(solo[1], self._chunk(lat.nx * lat.ny, lat.steps_per_launch))
+                if n > 0:
+                    lat.step(n)
+                    solo[1] -= n
+                ev = torch.cuda.Event()
+                ev.record(lat.stream)
+                inflight.append(ev)
+                if solo[1] == 0:
+                    solo[2] = ev
+            while len(inflight) > 2:
+                inflight.popleft().synchronize()
+            # nothing left to enqueue: wait for the next job to finish
+            idle = not running and (solo is None or solo[2] is not None)
+            finished = self.pool.poll(wait=idle and bool(pooled) and solo is None)
+            if solo is not None and solo[2] is not None:
+                if idle and not pooled:
+                    solo[2].synchronize()
+                if solo[2].query():
+                    finished.append(solo[0])
+                    solo = None
+                elif idle and not finished:
+                    time.sleep(2e-4)                 # a pooled and the lone job both finishing
             for lat in finished:
                 spec, admitted, need, _ = active.pop(id(lat))
                 status, diag = lat.diagnostics()

@@ -196,12 +196,12 @@ def test_status_strings():
 
 
 def test_default_shapes_by_size_and_storage():
-    # several steps per launch from 2^19 cells (FP32, FP64) or 2^21 cells
-    # (FP16, BF16), with segments of at least 8 rows; one step below
+    # several steps per launch from 2^19 cells for every storage type, with
+    # segments of at least 8 rows; one step below
     fake = 1 << 32
     cases = [("f32", 512, 512, 0), ("f32", 1024, 512, 13), ("f32", 1024, 1024, 13), ("f64", 1024, 1024, 13),
-             ("f16", 1024, 1024, 0), ("bf16", 2048, 512, 0), ("f16", 2048, 1024, 12), ("bf16", 4096, 4096, 12),
-             ("f32", 4096, 4096, 13)]
+             ("f16", 1024, 511, 0), ("bf16", 723, 723, 0), ("f16", 1024, 512, 12), ("bf16", 1024, 1024, 12),
+             ("f16", 2048, 1024, 12), ("bf16", 4096, 4096, 12), ("f32", 4096, 4096, 13)]
     for storage, nx, ny, variant in cases:
         d = desc(nx=nx, ny=ny)
         d.storage = _lib.STORAGE[storage]

@@ -207,12 +207,13 @@ def test_projection_matches_numpy_fourier_sum():
         assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want)) + tol_abs, (mx, my)
 
 
-@pytest.mark.parametrize("storage", ["f32", "f64"])
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16", "bf16"])
 def test_mid_size_default_is_several_steps_and_matches_the_oracle(storage):
     # 1100 x 480 = 528,000 cells (at least 2^19): the lattice starts with the
     # several-steps shared-halo shape with short segments (at least 8 rows),
     # whose last strip is partial; 45 steps are six 7-step passes and one
-    # 3-step pass.  Two pulses, one across the periodic seams in x and y.
+    # 3-step pass (FP32, FP64) or seven 6-step passes and one 3-step pass
+    # (FP16, BF16).  Two pulses, one across the periodic seams in x and y.
     nx, ny, steps, A = 1100, 480, 45, 1e-3
     s = t5a_rates()
     rho, ux, uy = lbm_inputs.gaussian_pulse(nx, ny, A, 9.0, center=(300.4, 210.7), u0=(0.05, 0.0))
@@ -220,7 +221,8 @@ def test_mid_size_default_is_several_steps_and_matches_the_oracle(storage):
     rho = rho + (rho2 - 1.0)
     lat = lattice(nx, ny, s, storage=storage, u0=(0.05, 0.0))
     c = lat.launch
-    assert c["variant"] == 13 and c["flags"] & 32 and c["rows"] >= 8, c
+    half = storage in ("f16", "bf16")
+    assert c["variant"] == (12 if half else 13) and c["flags"] & 32 and c["rows"] >= 8, c
     lat.init(rho, ux, uy).step(steps)
     ref = oracle.run(oracle.init(rho, ux, uy), s, steps)
     if storage == "f64":
@@ -228,6 +230,11 @@ def test_mid_size_default_is_several_steps_and_matches_the_oracle(storage):
         return
     rr, ur, vr = oracle.moments(ref)
     r, u, v = (np_(a) for a in lat.moments())
+    if half:
+        # the rounding bound of 16-bit storage, 3 u sqrt(steps) A
+        unit = 2.0 ** -11 if storage == "f16" else 2.0 ** -8
+        assert np.max(np.abs(r - rr)) <= 3.0 * unit * np.sqrt(steps) * A
+        return
     assert np.max(np.abs(r - rr)) <= 1e-5 * A
     Au = max(np.max(np.abs(ux - 0.05)), np.max(np.abs(uy)), np.max(np.abs(ur - 0.05)))
     assert np.max(np.abs(u - ur)) <= 1e-5 * Au

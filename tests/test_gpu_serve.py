@@ -54,6 +54,33 @@ def test_served_digests_equal_plain_digests():
     assert len(set(served.values())) == len(trace)                       # distinct jobs, distinct digests
 
 
+def test_lone_jobs_run_alone_join_the_pool_and_equal_plain_runs():
+    # A long job starts on an empty server and advances alone with its own
+    # launches; a second job arrives while it runs, so the first joins the
+    # pool with the steps it has left; a third arrives long after both and
+    # runs alone to the end.  Every final state equals its plain run's.
+    import dataclasses
+    from paper_1107_4543_amd.serve import Server, run_plain
+    base = small_trace(41, 3, rate=100.0, storages=("f32", "f16", "f32"))
+    trace = [dataclasses.replace(base[0], nx=512, ny=512, steps=5003, arrival=0.0, tag=0),
+             dataclasses.replace(base[1], nx=200, ny=136, steps=777, arrival=0.005, tag=1),
+             dataclasses.replace(base[2], nx=300, ny=260, steps=401, arrival=0.4, tag=2)]
+    srv = Server(1 << 34, max_members=8, chunk_ms=2.0, keep="state")
+    served = {r.tag: r for r in srv.run(trace)}
+    srv.close()
+    assert srv.solo_started == 2 and srv.solo_joined == 1, (srv.solo_started, srv.solo_joined)
+    off = Server(1 << 34, max_members=8, chunk_ms=2.0, keep="state", solo=False)
+    pooled = {r.tag: r for r in off.run(trace)}
+    off.close()
+    assert off.solo_started == 0
+    plain = {r.tag: r for r in run_plain(trace, keep="state")}
+    for s in trace:
+        assert served[s.tag].digest[0] == plain[s.tag].digest[0] == s.steps
+        assert torch.equal(served[s.tag].state, plain[s.tag].state), s.tag
+        assert torch.equal(pooled[s.tag].state, plain[s.tag].state), s.tag
+        assert served[s.tag].diag == plain[s.tag].diag
+
+
 def _oracle_fields(spec):
     import oracle
     from oracle import linear
@@ -74,12 +101,15 @@ def test_served_jobs_match_the_oracle():
     # Served jobs (in the mix) against the FP64 oracle run of the same job:
     # FP64 storage to 1e-12 of the field, FP32 to 1e-5 of the fluctuation
     # amplitude, 16-bit storage within 3 u sqrt(steps) A (u the unit roundoff
-    # of the stored type).
+    # of the stored type).  These jobs are short enough to finish alone
+    # between arrivals, so the lone-job path is off: every job runs in the
+    # pool's batched kernels (the lone path runs the plain launches, which the
+    # parity tests check against the oracle).
     from paper_1107_4543_amd.serve import Server
     trace = small_trace(31, 12, rate=500.0, storages=("f64", "f32", "f16", "bf16"), side_range=(24, 96),
                         steps_range=(20, 300))
     assert {s.storage for s in trace} == {"f64", "f32", "f16", "bf16"}
-    srv = Server(1 << 34, max_members=12, chunk_ms=2.0, keep="fields")
+    srv = Server(1 << 34, max_members=12, chunk_ms=2.0, keep="fields", solo=False)
     served = {r.tag: r for r in srv.run(trace)}
     srv.close()
     assert srv.peak_members >= 2
