@@ -15,9 +15,16 @@ a number of steps.  ``Server.run`` replays a trace of jobs in real time:
   generated on the device and it joins the pool (its state stays on the
   device for its whole life); a head that does not fit blocks the jobs
   behind it (no backfilling), which bounds its wait;
-* the pool advances all admitted jobs together, one chunk of steps at a time
-  (persistent batched launches, recorded step loop), with at most two chunks
-  in flight so that admissions and completions are handled between chunks;
+* the pool advances all admitted jobs together, one chunk of about
+  ``chunk_ms`` of device work at a time (persistent batched launches,
+  recorded step loop), with at most two rounds of chunks in flight so that
+  admissions and completions are handled between them.  Every member
+  advances by the same number of steps per chunk, so a small lattice beside
+  a large one moves at the large one's pace (a 128^2 job beside a 4096^2
+  one: ~70 steps per 5 ms chunk instead of over a thousand).  With
+  ``size_classes`` the jobs go to one pool per size class instead, whose
+  chunks take turns on one stream: small jobs then move at their own pace,
+  but the pools no longer share launches;
   a job admitted to an empty server with nothing queued behind it advances
   alone with its own lattice's default launches (``solo``), and joins the
   pool with its remaining steps as soon as a second job is admitted (every
@@ -215,16 +222,26 @@ class Server:
     nothing queued advances with its lattice's own default launches until a
     second job is admitted (the pool's batched kernels pay a table lookup
     and a launch shape shared by every member; one job alone runs faster
-    with the shape chosen for its lattice)."""
+    with the shape chosen for its lattice).  size_classes: the cell counts
+    that separate pools by lattice size (ascending; the default () puts
+    every job in one pool, which measured the higher aggregate rate and the
+    lower mean latency under load; classes gave the lower median)."""
 
     def __init__(self, hbm_budget_bytes, max_members=256, max_tiles=1 << 20, chunk_ms=5.0,
-                 device="cuda:0", screen=False, tune=False, policy="aged", max_active_cells=1 << 25,
-                 tile_cells=512, keep=None, solo=True):
+                 device="cuda:0", screen=False, policy="aged", max_active_cells=1 << 25,
+                 tile_cells=512, keep=None, solo=True, size_classes=()):
         self.device = torch.device(device)
         self.budget = int(hbm_budget_bytes)
-        self.pool = Pool(max_members=max_members, max_tiles=max_tiles, device=self.device)
-        self.pool.set_shape(tile_cells=tile_cells, block=512, grid=4096, graph_steps=256)
-        self.steps_per_launch = self.pool.shape["steps_per_launch"]
+        if list(size_classes) != sorted(set(size_classes)) or any(c <= 0 for c in size_classes):
+            raise ValueError(f"size_classes must be ascending positive cell counts, not {size_classes!r}")
+        self.size_classes = tuple(int(c) for c in size_classes)
+        self.pools = []
+        for _ in range(len(self.size_classes) + 1):
+            pool = Pool(max_members=max_members, max_tiles=max_tiles, device=self.device,
+                        stream=self.pools[0].stream if self.pools else None)
+            pool.set_shape(tile_cells=tile_cells, block=512, grid=4096, graph_steps=256)
+            self.pools.append(pool)
+        self.steps_per_launch = self.pools[0].shape["steps_per_launch"]
         self.max_members = max_members
         self.chunk_ms = chunk_ms
         if policy not in ("aged", "sjf", "fifo"):
@@ -234,7 +251,6 @@ class Server:
         self.max_active_cells = max_active_cells
         self.solo = solo
         self.screen = screen
-        self.tune = tune
         self.used = 0
         self.peak_used = 0
         self.peak_members = 0
@@ -249,6 +265,10 @@ class Server:
         # on, so a stream per server would keep every earlier server's job
         # memory reserved.
         self.side = _side_stream(self.device)
+
+    def _pool_of(self, spec):
+        cells = spec.nx * spec.ny
+        return self.pools[sum(1 for c in self.size_classes if cells >= c)]
 
     def _chunk_steps(self, active_cells):
         # about chunk_ms of device work at the pool's update rate (short steps
@@ -265,11 +285,10 @@ class Server:
         pending = collections.deque(sorted(trace, key=lambda s: s.arrival))
         queue = collections.deque()
         active = {}                                  # id(lattice) -> (spec, admitted, bytes, lattice)
-        inflight = collections.deque()
+        inflight = collections.deque()               # rounds: the events of one round of chunks
         results = []
-        stream = self.pool.stream
-        # the job advancing alone outside the pool: [lattice, steps not yet
-        # enqueued, event after its last step (once all are enqueued)]
+        # the job advancing alone outside the pools: [lattice, steps not yet
+        # enqueued, event after its last step (once all are enqueued), spec]
         solo = None
         t0 = time.perf_counter()
         while pending or queue or active:
@@ -291,17 +310,17 @@ class Server:
                     break
                 lat = _new_lattice(spec, self.device, self.side)
                 if self.solo and not active and len(queue) == 1:
-                    solo = [lat, spec.steps, None]
+                    solo = [lat, spec.steps, None, spec]
                     self.solo_started += 1
                 else:
                     if solo is not None and solo[1] > 0:
-                        # a second job: the lone one joins the pool with the
+                        # a second job: the lone one joins its pool with the
                         # steps it has left (the pool waits for its queued ones)
-                        self.pool.add(solo[0], solo[1])
+                        self._pool_of(solo[3]).add(solo[0], solo[1])
                         solo = None
                         self.solo_joined += 1
                     try:
-                        self.pool.add(lat, spec.steps)
+                        self._pool_of(spec).add(lat, spec.steps)
                     except _lib.LbmError as e:
                         if e.status != _lib.LBM_E_NOMEM or not active:
                             raise
@@ -313,13 +332,19 @@ class Server:
                 self.peak_used = max(self.peak_used, self.used)
                 self.peak_members = max(self.peak_members, len(active))
             solo_lat = solo[0] if solo is not None else None
-            pooled = [a for a in active.values() if a[3] is not solo_lat]
-            running = [a for a in pooled if self.pool.remaining(a[3]) > 0]
-            if running:
-                self.pool.step(self._chunk_steps(sum(a[0].nx * a[0].ny for a in running)))
+            streams = []
+            for pool in self.pools:
+                running = [a for a in active.values()
+                           if a[3] is not solo_lat and self._pool_of(a[0]) is pool and pool.remaining(a[3]) > 0]
+                if running:
+                    pool.step(self._chunk_steps(sum(a[0].nx * a[0].ny for a in running)))
+                    if all(pool.stream is not s for s in streams):
+                        streams.append(pool.stream)
+            events = []
+            for s in streams:
                 ev = torch.cuda.Event()
-                ev.record(stream)
-                inflight.append(ev)
+                ev.record(s)
+                events.append(ev)
             if solo is not None and solo[2] is None:
                 lat = solo[0]
                 n = min(solo[1], self._chunk(lat.nx * lat.ny, lat.steps_per_launch))
@@ -328,22 +353,26 @@ class Server:
                     solo[1] -= n
                 ev = torch.cuda.Event()
                 ev.record(lat.stream)
-                inflight.append(ev)
+                events.append(ev)
                 if solo[1] == 0:
                     solo[2] = ev
+            enqueued = bool(events)
+            if events:
+                inflight.append(events)
             while len(inflight) > 2:
-                inflight.popleft().synchronize()
-            # nothing left to enqueue: wait for the next job to finish
-            idle = not running and (solo is None or solo[2] is not None)
-            finished = self.pool.poll(wait=idle and bool(pooled) and solo is None)
-            if solo is not None and solo[2] is not None:
-                if idle and not pooled:
-                    solo[2].synchronize()
-                if solo[2].query():
-                    finished.append(solo[0])
-                    solo = None
-                elif idle and not finished:
-                    time.sleep(2e-4)                 # a pooled and the lone job both finishing
+                for ev in inflight.popleft():
+                    ev.synchronize()
+            finished = []
+            for pool in self.pools:
+                finished += pool.poll()
+            if solo is not None and solo[2] is not None and solo[2].query():
+                finished.append(solo[0])
+                solo = None
+            if not enqueued and not finished and inflight:
+                # every admitted job has all its steps enqueued: wait for the
+                # oldest round in flight, after which the next may be done
+                for ev in inflight.popleft():
+                    ev.synchronize()
             for lat in finished:
                 spec, admitted, need, _ = active.pop(id(lat))
                 status, diag = lat.diagnostics()
@@ -360,7 +389,8 @@ class Server:
         return results
 
     def close(self):
-        self.pool.close()
+        for pool in self.pools:
+            pool.close()
 
 
 def run_plain(trace, device="cuda:0", keep=None) -> List[JobResult]:

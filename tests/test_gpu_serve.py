@@ -81,6 +81,32 @@ def test_lone_jobs_run_alone_join_the_pool_and_equal_plain_runs():
         assert served[s.tag].diag == plain[s.tag].diag
 
 
+def test_small_jobs_advance_at_their_own_pace_beside_large_ones():
+    # A 2048^2 job starts alone; a 128^2 job with as many steps arrives while
+    # it runs.  In pools by size class (2^18 and 2^21 cells) the small job
+    # takes its steps in chunks of its own and finishes first; in one shared
+    # pool (the default) every member advances by the same steps per chunk,
+    # so it finishes with the large one.  Both equal plain runs bitwise.
+    import dataclasses
+    from paper_1107_4543_amd.serve import Server, run_plain
+    base = small_trace(43, 2, rate=100.0, storages=("f32", "f32"))
+    trace = [dataclasses.replace(base[0], nx=2048, ny=2048, steps=3000, arrival=0.0, tag=0),
+             dataclasses.replace(base[1], nx=128, ny=128, steps=3000, arrival=0.004, tag=1)]
+    srv = Server(1 << 34, max_members=8, keep="state", size_classes=(1 << 18, 1 << 21))
+    served = {r.tag: r for r in srv.run(trace)}
+    srv.close()
+    assert len(srv.pools) == 3 and srv.solo_joined == 1
+    assert served[1].done < served[0].done, (served[1].done, served[0].done)
+    one = Server(1 << 34, max_members=8, keep="state")
+    shared = {r.tag: r for r in one.run(trace)}
+    one.close()
+    assert len(one.pools) == 1
+    plain = {r.tag: r for r in run_plain(trace, keep="state")}
+    for s in trace:
+        assert torch.equal(served[s.tag].state, plain[s.tag].state), s.tag
+        assert torch.equal(shared[s.tag].state, plain[s.tag].state), s.tag
+
+
 def _oracle_fields(spec):
     import oracle
     from oracle import linear
