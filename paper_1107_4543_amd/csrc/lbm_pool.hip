@@ -183,11 +183,13 @@ int tiles_of(const lbm_pool_shape &sh, const lbm_lattice *L) { return onestep_ti
 // the device once (three four-wave workgroups per compute unit, the count a
 // single lattice's default measured best with, or eight single waves), as
 // with a few small members or one job of a
-// lightly loaded serving pool -- the height that gives about that many
-// tasks, at least 8 rows (as a single lattice's default shape: the pipeline
-// then repeats its 2(T-1) start-up rows often, yet a full device still
-// measured faster) and never above seg_rows, as long as the tile table holds
-// them.
+// lightly loaded serving pool -- the shortest height whose tasks still fit
+// in that one round (a task beyond it would run as a fourth workgroup on a
+// unit and stretch the launch; a lone 4096^2 lattice gets 45 segments of 91
+// rows per strip, 765 tasks, not 46 of 90, 782), at least 8 rows (as a
+// single lattice's default shape: the pipeline then repeats its 2(T-1)
+// start-up rows often, yet a full device still measured faster) and never
+// above seg_rows, as long as the tile table holds them.
 int table_seg_rows(const lbm_pool *P)
 {
     const lbm_pool_shape &sh = P->shape;
@@ -203,11 +205,15 @@ int table_seg_rows(const lbm_pool *P)
     const int64_t fill = (int64_t)lbm::device_cus() * (wg_table(sh) ? 3 : 8);
     if (tasks >= fill) return sh.seg_rows;
     const int low = std::min(sh.seg_rows, 8);
-    const int seg = (int)std::max<int64_t>(low, std::min<int64_t>(sh.seg_rows, strip_rows / fill));
-    int64_t need = onestep;
-    for (const Slot &sl : P->slots)
-        if (sl.lat && sl.t_done < sl.t_target) need += (int64_t)strips_of(sh, sl.lat) * segments_of(seg, sl.lat);
-    return need <= P->max_tiles ? seg : sh.seg_rows;
+    auto tasks_at = [&](int rows) {
+        int64_t n = 0;
+        for (const Slot &sl : P->slots)
+            if (sl.lat && sl.t_done < sl.t_target) n += (int64_t)strips_of(sh, sl.lat) * segments_of(rows, sl.lat);
+        return n;
+    };
+    int seg = (int)std::max<int64_t>(low, std::min<int64_t>(sh.seg_rows, strip_rows / fill));
+    while (seg < sh.seg_rows && tasks_at(seg) > fill) ++seg;
+    return onestep + tasks_at(seg) <= P->max_tiles ? seg : sh.seg_rows;
 }
 
 void drop_graphs(lbm_pool *P)
