@@ -252,8 +252,11 @@ def pool_roofline(T, cells, launches, ms, traffic=None, steps=None):
 
 # Pool shape measured fastest for batch256 on MI355X (seven steps per launch,
 # strip tasks of about 96 rows, one workgroup of 4 waves sharing its halo
-# columns through LDS per task, flags 32; the pool's initial shape).
-DEFAULT_POOL_SHAPE = "256,512,4096,256,7,96,4,32"
+# columns through LDS per task, a member's left-over columns in two-wave
+# workgroups when they fit: flags 96).  The pool's initial shape differs
+# only in flags 32 (left-over columns in a narrower four-wave strip), which
+# is faster for the few large lattices of a lightly loaded pool.
+DEFAULT_POOL_SHAPE = "256,512,4096,256,7,96,4,96"
 POOL_SHAPE_KEYS = ["tile_cells", "block", "grid", "graph_steps", "steps_per_launch", "seg_rows", "waves", "flags"]
 
 

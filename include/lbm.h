@@ -353,10 +353,11 @@ typedef struct lbm_pool lbm_pool;
  *                columns through LDS as for lbm_launch variants 10-13 with
  *                flag 32 (34 also loads one row ahead): four-wave strips of
  *                64 * 4 - 2(T-1) columns (rounded as there) from column 0,
- *                and the columns left over in one two-wave strip (64 * 2 -
- *                2(T-1) columns, rounded alike) when they fit it, else in
- *                one more, narrower, four-wave strip.  The two-wave
- *                workgroups run as a second launch beside the first.
+ *                and the columns left over in one more, narrower,
+ *                four-wave strip; or 96 or 98 (32 or 34 plus bit 6): the
+ *                same, except that left-over columns that fit one
+ *                two-wave strip (64 * 2 - 2(T-1) columns, rounded alike)
+ *                go to one, run as a second launch beside the first.
  * The tile table holds the one-step tiles and, for T > 1, the strip tasks
  * of every unfinished member. */
 typedef struct lbm_pool_shape {

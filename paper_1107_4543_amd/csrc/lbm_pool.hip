@@ -114,9 +114,17 @@ int strip_cols(const lbm_pool_shape &sh, const lbm_lattice *L)
 
 // Shared-halo tables (flags bit 5): strip tasks of one workgroup each, as
 // wide as its lanes allow: workgroups of kWgMaxWaves waves over a member's
-// columns from x = 0, and one of two waves for the columns left over when
-// they fit its strip (else one more, narrower, four-wave strip).
+// columns from x = 0, the columns left over in one more, narrower, four-wave
+// strip -- or, with flags bit 6 (kWgTwo) in the shape, in one two-wave strip
+// when they fit it.  The two-wave strips idle fewer lanes on narrow members
+// but run as a second kernel beside the four-wave one: within the spread on
+// the 256-lattice batch, and slower on a lone lattice with such columns
+// (2048^2: 241k against 280k MLUPS), so they are not the default.
 bool wg_table(const lbm_pool_shape &sh) { return sh.steps_per_launch > 1 && (sh.flags & lbm::kWgHalo) != 0; }
+
+// The shape's kernel flags (the four-wave kernel's template flags): the
+// table-layout bit kWgTwo removed.
+int kernel_flags(const lbm_pool_shape &sh) { return sh.flags & ~lbm::kWgTwo; }
 
 int task_cols(const lbm_pool_shape &sh, const lbm_lattice *L)
 {
@@ -138,8 +146,8 @@ WgStrips wg_strips(const lbm_pool_shape &sh, const lbm_lattice *L)
     const int w2 = lbm::multi_strip_cols(sh.steps_per_launch, elem_bytes(L), 128);
     g.n4 = L->v.nx / g.w4;
     const int rem = L->v.nx - g.n4 * g.w4;
-    g.two = rem > 0 && rem <= w2;
-    if (rem > w2) ++g.n4;
+    g.two = (sh.flags & lbm::kWgTwo) && rem > 0 && rem <= w2;
+    if (rem > 0 && !g.two) ++g.n4;
     return g;
 }
 
@@ -451,8 +459,8 @@ lbm_status get_graph(lbm_pool *P, unsigned mask, unsigned two, int len, int T, i
                                  (void *)&TT};
                 hipKernelNodeParams np{};
                 np.func = !multi    ? lbm::pool_step_kernel(c)
-                          : kind    ? lbm::pool_multi_kernel(c, T, P->shape.flags | lbm::kWgTwo)
-                                    : lbm::pool_multi_kernel(c, T, P->shape.flags);
+                          : kind    ? lbm::pool_multi_kernel(c, T, kernel_flags(P->shape) | lbm::kWgTwo)
+                                    : lbm::pool_multi_kernel(c, T, kernel_flags(P->shape));
                 np.gridDim = dim3(!multi ? grid : kind ? tgrid : mgrid);
                 np.blockDim = !multi ? dim3(P->shape.block) : dim3(64, kind ? 2 : P->shape.waves);
                 np.sharedMemBytes = 0;
@@ -505,8 +513,9 @@ int chunk_steps(const lbm_pool *P, int kk)
     if (T < 2 || kk >= T || kk < 2) return T;
     for (int r = 0; r < lbm::kRanges; ++r) {
         if (!(P->range_mask & (1u << r))) continue;
-        if (!lbm::pool_multi_kernel(r / lbm::kChains, kk, P->shape.flags)) return T;
-        if ((P->two_mask & (1u << r)) && !lbm::pool_multi_kernel(r / lbm::kChains, kk, P->shape.flags | lbm::kWgTwo))
+        if (!lbm::pool_multi_kernel(r / lbm::kChains, kk, kernel_flags(P->shape))) return T;
+        if ((P->two_mask & (1u << r)) &&
+            !lbm::pool_multi_kernel(r / lbm::kChains, kk, kernel_flags(P->shape) | lbm::kWgTwo))
             return T;
     }
     return kk;
@@ -556,9 +565,10 @@ bool valid_shape(const lbm_pool_shape &s)
                            (!(s.flags & lbm::kWgHalo) ||
                             (s.waves == lbm::kWgMaxWaves &&
                              lbm::pool_multi_kernel(LBM_STORE_F32 * 2 + LBM_COMPUTE_F32, s.steps_per_launch,
-                                                    s.flags | lbm::kWgTwo))) &&
-                           !(s.flags & lbm::kWgTwo) &&
-                           lbm::pool_multi_kernel(LBM_STORE_F32 * 2 + LBM_COMPUTE_F32, s.steps_per_launch, s.flags));
+                                                    kernel_flags(s) | lbm::kWgTwo))) &&
+                           (!(s.flags & lbm::kWgTwo) || (s.flags & lbm::kWgHalo)) &&
+                           lbm::pool_multi_kernel(LBM_STORE_F32 * 2 + LBM_COMPUTE_F32, s.steps_per_launch,
+                                                  kernel_flags(s)));
     return s.tile_cells >= 64 && s.tile_cells <= (1 << 22) && s.block >= 64 && s.block <= 1024 && s.block % 64 == 0 &&
            s.grid >= 1 && s.grid <= (1 << 20) && s.graph_steps >= 1 && s.graph_steps <= 1024 && multi_ok;
 }
@@ -827,13 +837,13 @@ lbm_status lbm_pool_time_launches(lbm_pool *pool, int32_t reps, double *avg_us)
     auto launch_all = [&]() -> hipError_t {
         for (int c = 0; c < lbm::kRanges; ++c) {
             if (!(pool->range_mask & (1u << c))) continue;
-            hipError_t r = T > 1 ? lbm::launch_pool_multi(c, T, pool->shape.flags, pool->d_hdr, pool->d_mem,
+            hipError_t r = T > 1 ? lbm::launch_pool_multi(c, T, kernel_flags(pool->shape), pool->d_hdr, pool->d_mem,
                                                           pool->d_tiles, 0, multi_grid(pool), pool->shape.waves,
                                                           pool->stream)
                                  : lbm::launch_pool_step(c, pool->d_hdr, pool->d_mem, pool->d_tiles, 0, 1, 1,
                                                          launch_grid(pool), pool->shape.block, pool->stream);
             if (r == hipSuccess && T > 1 && (pool->two_mask & (1u << c)))
-                r = lbm::launch_pool_multi(c, T, pool->shape.flags | lbm::kWgTwo, pool->d_hdr, pool->d_mem,
+                r = lbm::launch_pool_multi(c, T, kernel_flags(pool->shape) | lbm::kWgTwo, pool->d_hdr, pool->d_mem,
                                            pool->d_tiles, 0, two_grid(pool), 2, pool->stream);
             if (r != hipSuccess) return r;
         }
@@ -895,7 +905,7 @@ lbm_status lbm_pool_tune(lbm_pool *pool, int32_t reps, lbm_pool_shape *best, dou
     for (int T : {2, 4, 5, 6, 7})
         for (int seg : {32, 48, 64, 96, 128})
             for (int waves : {1, 4})
-                for (int flags : {0, 2, 12, 32, 34})           // 32, 34: four waves only
+                for (int flags : {0, 2, 12, 32, 34, 96, 98})   // 32 and up: four waves only
                     for (int grid : {4096, 16384, 65536}) {
                         lbm_pool_shape s = single;
                         s.steps_per_launch = T;

@@ -68,7 +68,8 @@ class Pool:
         several-steps-per-pass kernel (seg_rows rows, `waves` waves per
         workgroup, kernel flags 0, 2, 4 or 12 as for Lattice.set_launch, or
         32 / 34 with four waves: one workgroup per strip task, halo columns
-        shared through LDS)."""
+        shared through LDS; 96 / 98: the same with two-wave workgroups for
+        left-over columns that fit them)."""
         _lib.lbm_pool_set_shape(self._h, _lib.lbm_pool_shape(tile_cells, block, grid, graph_steps, steps_per_launch,
                                                              seg_rows, waves, flags))
         return self

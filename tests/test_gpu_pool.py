@@ -183,7 +183,9 @@ def test_full_batch_of_256_lattices_matches_alone_on_a_sample():
 # waves that pass their halo values through LDS.  Widths around the
 # workgroup strip (244 columns at T = 7 for 32-bit storage): an exact strip,
 # strips plus a narrow remainder, members narrower than a strip (whose lanes
-# wrap around the lattice) and a one-column member.
+# wrap around the lattice) and a one-column member.  Flags 32 / 34 put
+# left-over columns in a narrower four-wave strip, 96 / 98 in a two-wave one
+# when they fit it.
 WG_SIZES = [(600, 70), (200, 45), (257, 64), (64, 64), (1, 9), (490, 33), (244, 20), (31, 150), (1100, 12)]
 WG_STORES = ["f32", "f16", "f32", "bf16", "f32", "f64", "f32", "f16", "f32"]
 WG_STEPS = [37, 50, 23, 64, 5, 44, 71, 30, 19]
@@ -191,7 +193,12 @@ WG_SCHEDULES = [dict(steps_per_launch=7, seg_rows=13, waves=4, flags=32),
                    dict(steps_per_launch=7, seg_rows=40, waves=4, flags=34),
                    dict(steps_per_launch=6, seg_rows=9, waves=4, flags=32),
                    dict(steps_per_launch=4, seg_rows=16, waves=4, flags=34),
-                   dict(steps_per_launch=2, seg_rows=5, waves=4, flags=32)]
+                   dict(steps_per_launch=2, seg_rows=5, waves=4, flags=32),
+                   dict(steps_per_launch=7, seg_rows=13, waves=4, flags=96),
+                   dict(steps_per_launch=7, seg_rows=40, waves=4, flags=98),
+                   dict(steps_per_launch=6, seg_rows=9, waves=4, flags=96),
+                   dict(steps_per_launch=4, seg_rows=16, waves=4, flags=98),
+                   dict(steps_per_launch=2, seg_rows=5, waves=4, flags=96)]
 
 
 @pytest.mark.parametrize("sched", WG_SCHEDULES)
@@ -221,11 +228,14 @@ def test_shared_halo_tables_match_alone_bitwise(sched):
     pool.close()
 
 
-def test_shared_halo_table_member_parity_with_oracle_fp64():
+@pytest.mark.parametrize("flags", [32, 96])
+def test_shared_halo_table_member_parity_with_oracle_fp64(flags):
+    # 263 columns: one 244-column strip and 19 left over (a narrower
+    # four-wave strip with flags 32, a two-wave one with 96)
     from paper_1107_4543_amd.pool import Pool
     pool = Pool(max_members=4, max_tiles=1024)
     pool.set_shape(tile_cells=256, block=64, grid=16, graph_steps=14, steps_per_launch=7, seg_rows=11, waves=4,
-                   flags=32)
+                   flags=flags)
     s = [1.64, 1.54, 1.9, float(linear.s_from_nu(1e-3))]
     lat, (rho, ux, uy) = make(263, 30, s, "f64", seed=8, u0=(0.03, 0.0))
     pool.add(lat, 33)
@@ -237,20 +247,22 @@ def test_shared_halo_table_member_parity_with_oracle_fp64():
     pool.close()
 
 
-def test_shared_halo_shapes_need_four_waves_and_no_internal_bits():
-    # flag 32 tables run four-wave workgroups; bit 6 (two-wave workgroups)
-    # is internal to the pool's own launches, not a shape flag
+def test_shared_halo_shapes_need_four_waves_and_the_halo_bit():
+    # flag 32 tables run four-wave workgroups; bit 6 (two-wave workgroups for
+    # left-over columns) only goes with them (96, 98)
     from paper_1107_4543_amd import _lib
     from paper_1107_4543_amd.pool import Pool
     pool = Pool(max_members=2, max_tiles=256)
     for waves in (1, 2, 3):
-        with pytest.raises(_lib.LbmError) as e:
-            pool.set_shape(steps_per_launch=7, seg_rows=64, waves=waves, flags=32)
-        assert e.value.status == _lib.LBM_E_INVAL
-    for flags in (64, 96, 98):
+        for flags in (32, 96):
+            with pytest.raises(_lib.LbmError) as e:
+                pool.set_shape(steps_per_launch=7, seg_rows=64, waves=waves, flags=flags)
+            assert e.value.status == _lib.LBM_E_INVAL
+    for flags in (64, 66, 76):
         with pytest.raises(_lib.LbmError) as e:
             pool.set_shape(steps_per_launch=7, seg_rows=64, waves=4, flags=flags)
         assert e.value.status == _lib.LBM_E_INVAL
-    pool.set_shape(steps_per_launch=7, seg_rows=64, waves=4, flags=34)
-    assert pool.shape["flags"] == 34
+    for flags in (34, 96, 98):
+        pool.set_shape(steps_per_launch=7, seg_rows=64, waves=4, flags=flags)
+        assert pool.shape["flags"] == flags
     pool.close()
