@@ -204,8 +204,10 @@ def order_queue(queue, policy, now):
 _SIDE_STREAMS = {}
 
 
-def _side_stream(device):
-    key = torch.device(device).index or 0
+def _side_stream(device, name="side"):
+    """One stream per device and purpose, shared by every server of the
+    process (default priority)."""
+    key = (torch.device(device).index or 0, name)
     if key not in _SIDE_STREAMS:
         _SIDE_STREAMS[key] = torch.cuda.Stream(torch.device(device))
     return _SIDE_STREAMS[key]
@@ -222,14 +224,20 @@ class Server:
     nothing queued advances with its lattice's own default launches until a
     second job is admitted (the pool's batched kernels pay a table lookup
     and a launch shape shared by every member; one job alone runs faster
-    with the shape chosen for its lattice).  size_classes: the cell counts
+    with the shape chosen for its lattice).  solo_cells: jobs of at least
+    this many cells also keep their own launches (on a stream of their own,
+    beside the pool's) while no job waits in the queue, and join the pool
+    once one does; None (the default) leaves them to the pool.  Measured: a
+    lower median and mean at light load, a higher p99 (a large job beside a
+    concurrent pool is slowed more than in the pool, whose small members
+    barely slow it).  size_classes: the cell counts
     that separate pools by lattice size (ascending; the default () puts
     every job in one pool, which measured the higher aggregate rate and the
     lower mean latency under load; classes gave the lower median)."""
 
     def __init__(self, hbm_budget_bytes, max_members=256, max_tiles=1 << 20, chunk_ms=5.0,
                  device="cuda:0", screen=False, policy="aged", max_active_cells=1 << 25,
-                 tile_cells=512, keep=None, solo=True, size_classes=()):
+                 tile_cells=512, keep=None, solo=True, size_classes=(), solo_cells=None):
         self.device = torch.device(device)
         self.budget = int(hbm_budget_bytes)
         if list(size_classes) != sorted(set(size_classes)) or any(c <= 0 for c in size_classes):
@@ -250,6 +258,7 @@ class Server:
         self.keep = keep
         self.max_active_cells = max_active_cells
         self.solo = solo
+        self.solo_cells = solo_cells
         self.screen = screen
         self.used = 0
         self.peak_used = 0
@@ -265,6 +274,7 @@ class Server:
         # on, so a stream per server would keep every earlier server's job
         # memory reserved.
         self.side = _side_stream(self.device)
+        self.solo_stream = _side_stream(self.device, "solo")
 
     def _pool_of(self, spec):
         cells = spec.nx * spec.ny
@@ -287,9 +297,11 @@ class Server:
         active = {}                                  # id(lattice) -> (spec, admitted, bytes, lattice)
         inflight = collections.deque()               # rounds: the events of one round of chunks
         results = []
-        # the job advancing alone outside the pools: [lattice, steps not yet
-        # enqueued, event after its last step (once all are enqueued), spec]
-        solo = None
+        # jobs advancing outside the pools with their own launches, by
+        # id(lattice): [lattice, steps not yet enqueued, event after the
+        # last step (once all are enqueued), spec, large (joins a pool only
+        # when jobs wait in the queue; else when any other job is pooled)]
+        solos = {}
         t0 = time.perf_counter()
         while pending or queue or active:
             now = time.perf_counter() - t0
@@ -308,17 +320,23 @@ class Server:
                 if (self.used + need > self.budget or len(active) >= self.max_members
                         or (active and active_cells + spec.nx * spec.ny > self.max_active_cells)):
                     break
-                lat = _new_lattice(spec, self.device, self.side)
-                if self.solo and not active and len(queue) == 1:
-                    solo = [lat, spec.steps, None, spec]
+                big = self.solo_cells is not None and spec.nx * spec.ny >= self.solo_cells
+                backlog = len(queue) > 1                 # others wait behind this job
+                alone = self.solo and not active and not backlog
+                own = alone or (big and not backlog)
+                lat = _new_lattice(spec, self.device, self.solo_stream if big and own else self.side)
+                if own:
+                    solos[id(lat)] = [lat, spec.steps, None, spec, big]
                     self.solo_started += 1
                 else:
-                    if solo is not None and solo[1] > 0:
-                        # a second job: the lone one joins its pool with the
-                        # steps it has left (the pool waits for its queued ones)
-                        self._pool_of(solo[3]).add(solo[0], solo[1])
-                        solo = None
-                        self.solo_joined += 1
+                    for k, e in list(solos.items()):
+                        if e[1] > 0 and (not e[4] or backlog):
+                            # a second job: the lone one joins its pool with
+                            # the steps it has left (the pool waits for its
+                            # queued ones)
+                            self._pool_of(e[3]).add(e[0], e[1])
+                            del solos[k]
+                            self.solo_joined += 1
                     try:
                         self._pool_of(spec).add(lat, spec.steps)
                     except _lib.LbmError as e:
@@ -331,11 +349,10 @@ class Server:
                 self.used += need
                 self.peak_used = max(self.peak_used, self.used)
                 self.peak_members = max(self.peak_members, len(active))
-            solo_lat = solo[0] if solo is not None else None
             streams = []
             for pool in self.pools:
                 running = [a for a in active.values()
-                           if a[3] is not solo_lat and self._pool_of(a[0]) is pool and pool.remaining(a[3]) > 0]
+                           if id(a[3]) not in solos and self._pool_of(a[0]) is pool and pool.remaining(a[3]) > 0]
                 if running:
                     pool.step(self._chunk_steps(sum(a[0].nx * a[0].ny for a in running)))
                     if all(pool.stream is not s for s in streams):
@@ -345,17 +362,19 @@ class Server:
                 ev = torch.cuda.Event()
                 ev.record(s)
                 events.append(ev)
-            if solo is not None and solo[2] is None:
-                lat = solo[0]
-                n = min(solo[1], self._chunk(lat.nx * lat.ny, lat.steps_per_launch))
+            for e in solos.values():
+                if e[2] is not None:
+                    continue
+                lat = e[0]
+                n = min(e[1], self._chunk(lat.nx * lat.ny, lat.steps_per_launch))
                 if n > 0:
                     lat.step(n)
-                    solo[1] -= n
+                    e[1] -= n
                 ev = torch.cuda.Event()
                 ev.record(lat.stream)
                 events.append(ev)
-                if solo[1] == 0:
-                    solo[2] = ev
+                if e[1] == 0:
+                    e[2] = ev
             enqueued = bool(events)
             if events:
                 inflight.append(events)
@@ -365,9 +384,10 @@ class Server:
             finished = []
             for pool in self.pools:
                 finished += pool.poll()
-            if solo is not None and solo[2] is not None and solo[2].query():
-                finished.append(solo[0])
-                solo = None
+            for k, e in list(solos.items()):
+                if e[2] is not None and e[2].query():
+                    finished.append(e[0])
+                    del solos[k]
             if not enqueued and not finished and inflight:
                 # every admitted job has all its steps enqueued: wait for the
                 # oldest round in flight, after which the next may be done

@@ -73,11 +73,18 @@ def test_lone_jobs_run_alone_join_the_pool_and_equal_plain_runs():
     pooled = {r.tag: r for r in off.run(trace)}
     off.close()
     assert off.solo_started == 0
+    # the 512^2 job counted as large: it keeps its own launches while the
+    # second job runs in the pool beside it
+    big = Server(1 << 34, max_members=8, chunk_ms=2.0, keep="state", solo_cells=1 << 18)
+    beside = {r.tag: r for r in big.run(trace)}
+    big.close()
+    assert big.solo_started == 2 and big.solo_joined == 0, (big.solo_started, big.solo_joined)
     plain = {r.tag: r for r in run_plain(trace, keep="state")}
     for s in trace:
         assert served[s.tag].digest[0] == plain[s.tag].digest[0] == s.steps
         assert torch.equal(served[s.tag].state, plain[s.tag].state), s.tag
         assert torch.equal(pooled[s.tag].state, plain[s.tag].state), s.tag
+        assert torch.equal(beside[s.tag].state, plain[s.tag].state), s.tag
         assert served[s.tag].diag == plain[s.tag].diag
 
 
