@@ -18,7 +18,9 @@ a number of steps.  ``Server.run`` replays a trace of jobs in real time:
 * the pool advances all admitted jobs together, one chunk of about
   ``chunk_ms`` of device work at a time (persistent batched launches,
   recorded step loop), with at most two rounds of chunks in flight so that
-  admissions and completions are handled between them.  Every member
+  admissions and completions are handled between them; jobs with 16-bit
+  storage have a pool of their own (``half_pool``), with the launch shape
+  that suits them, whose chunks run beside the main pool's.  Every member
   advances by the same number of steps per chunk, so a small lattice beside
   a large one moves at the large one's pace (a 128^2 job beside a 4096^2
   one: ~70 steps per 5 ms chunk instead of over a thousand).  With
@@ -230,14 +232,18 @@ class Server:
     once one does; None (the default) leaves them to the pool.  Measured: a
     lower median and mean at light load, a higher p99 (a large job beside a
     concurrent pool is slowed more than in the pool, whose small members
-    barely slow it).  size_classes: the cell counts
+    barely slow it).  half_pool: jobs with 16-bit storage go to a pool of
+    their own, with six steps per launch and loads one row ahead (their
+    single-lattice shape; the main pool's seven steps suit FP32), on a
+    stream of its own beside the main pool's; measured a 20-25 % lower
+    median under load for 1-3 % of the aggregate.  size_classes: the cell counts
     that separate pools by lattice size (ascending; the default () puts
     every job in one pool, which measured the higher aggregate rate and the
     lower mean latency under load; classes gave the lower median)."""
 
     def __init__(self, hbm_budget_bytes, max_members=256, max_tiles=1 << 20, chunk_ms=5.0,
                  device="cuda:0", screen=False, policy="aged", max_active_cells=1 << 25,
-                 tile_cells=512, keep=None, solo=True, size_classes=(), solo_cells=None):
+                 tile_cells=512, keep=None, solo=True, size_classes=(), solo_cells=None, half_pool=True):
         self.device = torch.device(device)
         self.budget = int(hbm_budget_bytes)
         if list(size_classes) != sorted(set(size_classes)) or any(c <= 0 for c in size_classes):
@@ -249,7 +255,17 @@ class Server:
                         stream=self.pools[0].stream if self.pools else None)
             pool.set_shape(tile_cells=tile_cells, block=512, grid=4096, graph_steps=256)
             self.pools.append(pool)
+        self.half_pool = None
+        if half_pool:
+            # 16-bit storage in a pool of its own with the shape that suits it
+            # (six steps per launch, loads one row ahead), on its own stream
+            self.half_pool = Pool(max_members=max_members, max_tiles=max_tiles, device=self.device,
+                                  stream=_side_stream(self.device, "half"))
+            self.half_pool.set_shape(tile_cells=tile_cells, block=512, grid=4096, graph_steps=256,
+                                     steps_per_launch=6, flags=34)
+            self.pools.append(self.half_pool)
         self.steps_per_launch = self.pools[0].shape["steps_per_launch"]
+        self._spl = {id(p): p.shape["steps_per_launch"] for p in self.pools}
         self.max_members = max_members
         self.chunk_ms = chunk_ms
         if policy not in ("aged", "sjf", "fifo"):
@@ -277,14 +293,16 @@ class Server:
         self.solo_stream = _side_stream(self.device, "solo")
 
     def _pool_of(self, spec):
+        if self.half_pool is not None and spec.storage in ("f16", "bf16"):
+            return self.half_pool
         cells = spec.nx * spec.ny
         return self.pools[sum(1 for c in self.size_classes if cells >= c)]
 
-    def _chunk_steps(self, active_cells):
+    def _chunk_steps(self, active_cells, pool=None):
         # about chunk_ms of device work at the pool's update rate (short steps
         # are bounded below by launch cost), in whole T-step launches: a count
         # that is not a multiple of T ends every chunk in one-step launches
-        return self._chunk(active_cells, self.steps_per_launch)
+        return self._chunk(active_cells, self._spl[id(pool)] if pool is not None else self.steps_per_launch)
 
     def _chunk(self, cells, spl):
         est_ms = max(cells / SERVICE_LUPS_ESTIMATE * 1e3, 0.004)
@@ -354,7 +372,7 @@ class Server:
                 running = [a for a in active.values()
                            if id(a[3]) not in solos and self._pool_of(a[0]) is pool and pool.remaining(a[3]) > 0]
                 if running:
-                    pool.step(self._chunk_steps(sum(a[0].nx * a[0].ny for a in running)))
+                    pool.step(self._chunk_steps(sum(a[0].nx * a[0].ny for a in running), pool))
                     if all(pool.stream is not s for s in streams):
                         streams.append(pool.stream)
             events = []

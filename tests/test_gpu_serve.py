@@ -27,6 +27,8 @@ def test_served_jobs_equal_plain_runs_and_respect_the_budget(policy):
     budget = 3 * max(footprint(s) for s in trace)          # at most ~3 jobs at once
     srv = Server(budget, max_members=8, chunk_ms=2.0, policy=policy, keep="state")
     served = {r.tag: r for r in srv.run(trace)}
+    # FP16/BF16 jobs run in a pool of their own (six steps per launch)
+    assert srv.half_pool is srv.pools[-1] and srv.half_pool.shape["steps_per_launch"] == 6
     srv.close()
     assert srv.peak_used <= budget and srv.peak_members >= 2
     assert sorted(served) == [s.tag for s in trace] and not srv.rejected
@@ -99,12 +101,12 @@ def test_small_jobs_advance_at_their_own_pace_beside_large_ones():
     base = small_trace(43, 2, rate=100.0, storages=("f32", "f32"))
     trace = [dataclasses.replace(base[0], nx=2048, ny=2048, steps=3000, arrival=0.0, tag=0),
              dataclasses.replace(base[1], nx=128, ny=128, steps=3000, arrival=0.004, tag=1)]
-    srv = Server(1 << 34, max_members=8, keep="state", size_classes=(1 << 18, 1 << 21))
+    srv = Server(1 << 34, max_members=8, keep="state", size_classes=(1 << 18, 1 << 21), half_pool=False)
     served = {r.tag: r for r in srv.run(trace)}
     srv.close()
     assert len(srv.pools) == 3 and srv.solo_joined == 1
     assert served[1].done < served[0].done, (served[1].done, served[0].done)
-    one = Server(1 << 34, max_members=8, keep="state")
+    one = Server(1 << 34, max_members=8, keep="state", half_pool=False)
     shared = {r.tag: r for r in one.run(trace)}
     one.close()
     assert len(one.pools) == 1
