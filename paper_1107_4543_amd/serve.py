@@ -21,9 +21,10 @@ a number of steps.  ``Server.run`` replays a trace of jobs in real time:
   admissions and completions are handled between them; jobs with 16-bit
   storage have a pool of their own (``half_pool``), with the launch shape
   that suits them, whose chunks run beside the main pool's.  Every member
-  advances by the same number of steps per chunk, so a small lattice beside
-  a large one moves at the large one's pace (a 128^2 job beside a 4096^2
-  one: ~70 steps per 5 ms chunk instead of over a thousand).  With
+  of a pool advances by the same number of steps per chunk, so a small
+  lattice beside a large one moves at the large one's pace (a 128^2 job
+  beside a 4096^2 one: ~70 steps per 5 ms chunk instead of over a
+  thousand).  With
   ``size_classes`` the jobs go to one pool per size class instead, whose
   chunks take turns on one stream: small jobs then move at their own pace,
   but the pools no longer share launches;
@@ -218,9 +219,10 @@ def _side_stream(device, name="side"):
 class Server:
     """policy: "aged" (default) admits the queued job with the least work
     (cells x steps) first unless a job has aged (see order_queue), "sjf" the
-    one with the least work, "fifo" in arrival order.  max_active_cells caps the cells being advanced
-    at once (enough to fill the GPU; more only stretches every job's
-    latency), in addition to the HBM budget and the member slots.  keep:
+    one with the least work, "fifo" in arrival order.  max_active_cells caps
+    the cells being advanced at once (enough to fill the GPU; more only
+    stretches every job's latency), in addition to the HBM budget and the
+    member slots.  keep:
     what each JobResult carries besides the diagnostics (None, "digest",
     "state" or "fields").  solo: a job admitted to an empty server with
     nothing queued advances with its lattice's own default launches until a
@@ -235,8 +237,9 @@ class Server:
     barely slow it).  half_pool: jobs with 16-bit storage go to a pool of
     their own, with six steps per launch and loads one row ahead (their
     single-lattice shape; the main pool's seven steps suit FP32), on a
-    stream of its own beside the main pool's; measured a 20-25 % lower
-    median under load for 1-3 % of the aggregate.  size_classes: the cell counts
+    stream of its own beside the main pool's; measured a 10-25 % lower
+    median under load, p99 and aggregate within a few percent either way.
+    size_classes: the cell counts
     that separate pools by lattice size (ascending; the default () puts
     every job in one pool, which measured the higher aggregate rate and the
     lower mean latency under load; classes gave the lower median)."""
