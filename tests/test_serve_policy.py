@@ -122,3 +122,24 @@ def test_aged_wait_bound_does_not_grow_with_the_burst():
     w30 = simulate("aged", jobs30, cap, lups)[-1] - 0.5
     w60 = simulate("aged", jobs60, cap, lups)[-1] - 0.5
     assert abs(w60 - w30) <= 0.01
+
+
+def test_chunks_are_whole_launches_of_about_chunk_ms():
+    # a chunk is about chunk_ms of device work at the assumed update rate, at
+    # most 1024 steps, and a whole number of T-step launches when it is at
+    # least one launch long (a lone job or a pool advances in chunks of it)
+    serve = _serve_module()
+    srv = types.SimpleNamespace(chunk_ms=5.0)
+    for T in (1, 6, 7):
+        for cells in (128 * 128, 724 * 724, 2048 * 2048, 4096 * 4096, 1 << 25):
+            n = serve.Server._chunk(srv, cells, T)
+            assert 1 <= n <= 1024
+            if n >= T:
+                assert n % T == 0, (T, cells, n)
+            # within one launch of the target duration, or at the step cap
+            want = 5.0 / max(cells / serve.SERVICE_LUPS_ESTIMATE * 1e3, 0.004)
+            assert n <= want and (n + T > min(want, 1024) or n == 1024 - 1024 % T), (T, cells, n, want)
+    # a 4096^2 lattice: ~5 ms at 2.5e11 updates/s is 74 steps, 70 in seven-step launches
+    assert serve.Server._chunk(srv, 4096 * 4096, 7) == 70
+    # small lattices are bounded by the step cap
+    assert serve.Server._chunk(srv, 128 * 128, 7) == 1022
