@@ -561,7 +561,7 @@ def main():
     ap.add_argument("--rates", default="10,30,100,300,1000", help="serve: arrival rates (jobs/s)")
     ap.add_argument("--jobs", type=int, default=200, help="serve: jobs per rate")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget for admitted jobs")
-    ap.add_argument("--no-tune", action="store_true", help="use the library's default launch shape (four steps per launch from 2^22 cells)")
+    ap.add_argument("--no-tune", action="store_true", help="use the library's default launch shape (several steps per launch from 2^19 cells)")
     ap.add_argument("--tune", action="store_true", help="search the launch shape with lbm_tune before timing")
     ap.add_argument("--launch", default=None,
                     help="launch shape variant,block_x,block_y,rows,xcd_remap,flags (default: the recorded "

@@ -436,7 +436,7 @@ class Server:
 
 def run_plain(trace, device="cuda:0", keep=None) -> List[JobResult]:
     """One job at a time in arrival order, each with its lattice's default
-    launch shape (several steps per launch from 2^22 cells, else one)."""
+    launch shape (several steps per launch from 2^19 cells, else one)."""
     results = []
     t0 = time.perf_counter()
     for spec in sorted(trace, key=lambda s: s.arrival):
