@@ -189,7 +189,9 @@ int tiles_of(const lbm_pool_shape &sh, const lbm_lattice *L) { return onestep_ti
 // Segment height of a pool's table: the shape's seg_rows, or -- when the
 // unfinished members' strips cut at that height give fewer tasks than fill
 // the device once (three four-wave workgroups per compute unit, the count a
-// single lattice's default measured best with, or eight single waves), as
+// single lattice's default measured best with, or eight single waves; when
+// every member has FP64 storage two workgroups, and seg_rows counts half as
+// tall again), as
 // with a few small members or one job of a
 // lightly loaded serving pool -- the shortest height whose tasks still fit
 // in that one round (a task beyond it would run as a fourth workgroup on a
@@ -202,26 +204,31 @@ int table_seg_rows(const lbm_pool *P)
 {
     const lbm_pool_shape &sh = P->shape;
     if (sh.steps_per_launch < 2) return sh.seg_rows;
-    int64_t strip_rows = 0, tasks = 0, onestep = 0;
+    int64_t strip_rows = 0, onestep = 0;
+    bool all_f64 = true;
     for (const Slot &sl : P->slots) {
         if (!sl.lat || sl.t_done >= sl.t_target) continue;
-        const int n = strips_of(sh, sl.lat);
-        strip_rows += (int64_t)n * sl.lat->v.ny;
-        tasks += (int64_t)n * segments_of(sh.seg_rows, sl.lat);
+        strip_rows += (int64_t)strips_of(sh, sl.lat) * sl.lat->v.ny;
         onestep += onestep_tiles_of(sh, sl.lat);
+        all_f64 = all_f64 && sl.lat->v.storage == LBM_STORE_F64;
     }
-    const int64_t fill = (int64_t)lbm::device_cus() * (wg_table(sh) ? 3 : 8);
-    if (tasks >= fill) return sh.seg_rows;
-    const int low = std::min(sh.seg_rows, 8);
+    // FP64 storage: its workgroups hold about 250 registers per lane, so two
+    // fit a compute unit, not three, and a full device takes segments half as
+    // tall again as the shape's (as a single FP64 lattice's default)
+    const bool wide = wg_table(sh) && all_f64;
+    const int cap = wide ? std::min(4096, sh.seg_rows * 3 / 2) : sh.seg_rows;
+    const int64_t fill = (int64_t)lbm::device_cus() * (wg_table(sh) ? (wide ? 2 : 3) : 8);
     auto tasks_at = [&](int rows) {
         int64_t n = 0;
         for (const Slot &sl : P->slots)
             if (sl.lat && sl.t_done < sl.t_target) n += (int64_t)strips_of(sh, sl.lat) * segments_of(rows, sl.lat);
         return n;
     };
-    int seg = (int)std::max<int64_t>(low, std::min<int64_t>(sh.seg_rows, strip_rows / fill));
-    while (seg < sh.seg_rows && tasks_at(seg) > fill) ++seg;
-    return onestep + tasks_at(seg) <= P->max_tiles ? seg : sh.seg_rows;
+    if (tasks_at(cap) >= fill) return cap;
+    const int low = std::min(cap, 8);
+    int seg = (int)std::max<int64_t>(low, std::min<int64_t>(cap, strip_rows / fill));
+    while (seg < cap && tasks_at(seg) > fill) ++seg;
+    return onestep + tasks_at(seg) <= P->max_tiles ? seg : cap;
 }
 
 void drop_graphs(lbm_pool *P)
