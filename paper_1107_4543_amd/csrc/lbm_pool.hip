@@ -190,8 +190,9 @@ int tiles_of(const lbm_pool_shape &sh, const lbm_lattice *L) { return onestep_ti
 // unfinished members' strips cut at that height give fewer tasks than fill
 // the device once (three four-wave workgroups per compute unit, the count a
 // single lattice's default measured best with, or eight single waves; when
-// every member has FP64 storage two workgroups, and seg_rows counts half as
-// tall again), as
+// every member has FP64 storage two workgroups, with seg_rows counting half
+// as tall again, when every member has 16-bit storage four, with seg_rows
+// counting three quarters as tall), as
 // with a few small members or one job of a
 // lightly loaded serving pool -- the shortest height whose tasks still fit
 // in that one round (a task beyond it would run as a fourth workgroup on a
@@ -205,19 +206,28 @@ int table_seg_rows(const lbm_pool *P)
     const lbm_pool_shape &sh = P->shape;
     if (sh.steps_per_launch < 2) return sh.seg_rows;
     int64_t strip_rows = 0, onestep = 0;
-    bool all_f64 = true;
+    bool all_f64 = true, all_half = true;
     for (const Slot &sl : P->slots) {
         if (!sl.lat || sl.t_done >= sl.t_target) continue;
         strip_rows += (int64_t)strips_of(sh, sl.lat) * sl.lat->v.ny;
         onestep += onestep_tiles_of(sh, sl.lat);
-        all_f64 = all_f64 && sl.lat->v.storage == LBM_STORE_F64;
+        const int st = sl.lat->v.storage;
+        all_f64 = all_f64 && st == LBM_STORE_F64;
+        all_half = all_half && (st == LBM_STORE_F16 || st == LBM_STORE_BF16);
     }
-    // FP64 storage: its workgroups hold about 250 registers per lane, so two
-    // fit a compute unit, not three, and a full device takes segments half as
-    // tall again as the shape's (as a single FP64 lattice's default)
-    const bool wide = wg_table(sh) && all_f64;
-    const int cap = wide ? std::min(4096, sh.seg_rows * 3 / 2) : sh.seg_rows;
-    const int64_t fill = (int64_t)lbm::device_cus() * (wg_table(sh) ? (wide ? 2 : 3) : 8);
+    // Workgroups per compute unit, as a single lattice's default for the
+    // storage type: FP64 workgroups hold about 250 registers per lane, so two
+    // fit, with segments half as tall again as the shape's; 16-bit ones hold
+    // at most 120, so four fit, with segments three quarters as tall
+    int per_cu = 3, cap = sh.seg_rows;
+    if (wg_table(sh) && all_f64) {
+        per_cu = 2;
+        cap = std::min(4096, sh.seg_rows * 3 / 2);
+    } else if (wg_table(sh) && all_half) {
+        per_cu = 4;
+        cap = std::max(1, sh.seg_rows * 3 / 4);
+    }
+    const int64_t fill = (int64_t)lbm::device_cus() * (wg_table(sh) ? per_cu : 8);
     auto tasks_at = [&](int rows) {
         int64_t n = 0;
         for (const Slot &sl : P->slots)
