@@ -354,8 +354,14 @@ class Server:
                         if e[1] > 0 and (not e[4] or backlog):
                             # a second job: the lone one joins its pool with
                             # the steps it has left (the pool waits for its
-                            # queued ones)
-                            self._pool_of(e[3]).add(e[0], e[1])
+                            # queued ones); with the pool's tile table full it
+                            # keeps its own launches
+                            try:
+                                self._pool_of(e[3]).add(e[0], e[1])
+                            except _lib.LbmError as err:
+                                if err.status != _lib.LBM_E_NOMEM:
+                                    raise
+                                continue
                             del solos[k]
                             self.solo_joined += 1
                     try:
