@@ -234,11 +234,14 @@ int table_seg_rows(const lbm_pool *P)
             if (sl.lat && sl.t_done < sl.t_target) n += (int64_t)strips_of(sh, sl.lat) * segments_of(rows, sl.lat);
         return n;
     };
-    if (tasks_at(cap) >= fill) return cap;
+    // any height other than seg_rows must leave the table room (lbm_pool_add
+    // counted every member's tasks at seg_rows)
+    auto fits = [&](int rows) { return rows >= sh.seg_rows || onestep + tasks_at(rows) <= P->max_tiles; };
+    if (tasks_at(cap) >= fill) return fits(cap) ? cap : sh.seg_rows;
     const int low = std::min(cap, 8);
     int seg = (int)std::max<int64_t>(low, std::min<int64_t>(cap, strip_rows / fill));
     while (seg < cap && tasks_at(seg) > fill) ++seg;
-    return onestep + tasks_at(seg) <= P->max_tiles ? seg : cap;
+    return fits(seg) ? seg : (fits(cap) ? cap : sh.seg_rows);
 }
 
 void drop_graphs(lbm_pool *P)

@@ -266,3 +266,69 @@ def test_shared_halo_shapes_need_four_waves_and_the_halo_bit():
         pool.set_shape(steps_per_launch=7, seg_rows=64, waves=4, flags=flags)
         assert pool.shape["flags"] == flags
     pool.close()
+
+
+def test_shorter_segments_never_outgrow_the_tile_table():
+    # A pool of 16-bit members that fills four workgroups per compute unit
+    # cuts its strips at 0.75 x seg_rows, which makes more tasks than
+    # lbm_pool_add counts (at seg_rows).  With the smallest tile table that
+    # accepts two FP16 4096^2 members, the pool keeps seg_rows and steps;
+    # the results equal the members' own runs.
+    import torch
+    from paper_1107_4543_amd import Lattice, _lib
+    from paper_1107_4543_amd.pool import Pool
+    s = SETS[0]
+    nx = ny = 4096
+
+    def fields(seed):
+        rng = np.random.default_rng(seed)
+        return [torch.as_tensor(a, device="cuda:0") for a in
+                (1.0 + 1e-3 * rng.standard_normal((ny, nx)), 1e-3 * rng.standard_normal((ny, nx)),
+                 1e-3 * rng.standard_normal((ny, nx)))]
+
+    f = [fields(70), fields(71)]
+    lats = [Lattice(nx, ny, *s, storage="f16", device="cuda:0", scale_exp=22).init(*f[i]) for i in range(2)]
+    shape = dict(tile_cells=512, block=512, grid=4096, graph_steps=16, steps_per_launch=6, seg_rows=96, waves=4,
+                 flags=34)
+
+    def accepts(max_tiles):
+        # members with steps to go count their tiles; nothing is stepped
+        pool = Pool(max_members=4, max_tiles=max_tiles)
+        pool.set_shape(**shape)
+        added = []
+        try:
+            for lat in lats:
+                pool.add(lat, 8)
+                added.append(lat)
+            return True
+        except _lib.LbmError as e:
+            assert e.status == _lib.LBM_E_NOMEM
+            return False
+        finally:
+            for lat in added:
+                pool.remove(lat)
+            pool.close()
+
+    lo, hi = 1, 1 << 18                       # accepts(hi), not accepts(lo)
+    assert accepts(hi) and not accepts(lo)
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if accepts(mid):
+            hi = mid
+        else:
+            lo = mid
+    pool = Pool(max_members=4, max_tiles=hi)
+    pool.set_shape(**shape)
+    for lat in lats:
+        pool.add(lat, 8)
+    pool.step(8)
+    done = []
+    while pool.members:
+        done += pool.poll(wait=True)
+    pool.close()
+    assert len(done) == 2
+    for i, lat in enumerate(lats):
+        tw = Lattice(nx, ny, *s, storage="f16", device="cuda:0", scale_exp=22).init(*f[i]).step(8)
+        assert lat.t == 8 and torch.equal(lat.populations(), tw.populations()), i
+        tw.close()
+        lat.close()
