@@ -239,3 +239,31 @@ def test_mid_size_default_is_several_steps_and_matches_the_oracle(storage):
     Au = max(np.max(np.abs(ux - 0.05)), np.max(np.abs(uy)), np.max(np.abs(ur - 0.05)))
     assert np.max(np.abs(u - ur)) <= 1e-5 * Au
     assert np.max(np.abs(v - vr)) <= 1e-5 * Au
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+@pytest.mark.parametrize("nx,ny", [(1 << 20, 3), (3, 1 << 20)])
+def test_extreme_aspect_lattices_take_the_default_shape_and_match_the_oracle(storage, nx, ny):
+    # 2^20 x 3 and 3 x 2^20 cells (over 2^19: the several-steps default):
+    # 4298 strips of one 3-row segment, or one strip whose lanes wrap the
+    # 3 columns many times, cut into 768 segments of about 1366 rows; 13
+    # steps are a 7-step and a 6-step pass.  Random fields of amplitude A.
+    steps, A = 13, 1e-3
+    rng = np.random.default_rng(nx + 7 * ny)
+    rho = 1.0 + A * rng.standard_normal((ny, nx))
+    ux = 0.03 + A * rng.standard_normal((ny, nx))
+    uy = A * rng.standard_normal((ny, nx))
+    s = t5a_rates()
+    lat = lattice(nx, ny, s, storage=storage, u0=(0.03, 0.0))
+    c = lat.launch
+    assert c["variant"] == 13 and c["flags"] & 32, c
+    lat.init(rho, ux, uy).step(steps)
+    ref = oracle.run(oracle.init(rho, ux, uy), s, steps)
+    if storage == "f64":
+        check_f64(lat, ref)
+        return
+    rr, ur, vr = oracle.moments(ref)
+    r, u, v = (np_(a) for a in lat.moments())
+    assert np.max(np.abs(r - rr)) <= 1e-5 * A
+    assert np.max(np.abs(u - ur)) <= 1e-5 * A
+    assert np.max(np.abs(v - vr)) <= 1e-5 * A
