@@ -332,3 +332,28 @@ def test_shorter_segments_never_outgrow_the_tile_table():
         assert lat.t == 8 and torch.equal(lat.populations(), tw.populations()), i
         tw.close()
         lat.close()
+
+
+def test_extreme_aspect_members_match_alone_bitwise():
+    # 2^20 x 3 (4298 strips of one short segment) and 3 x 2^20 (one strip
+    # whose lanes wrap the three columns, cut into many segments) in one pool
+    # with its initial shape, 13 steps; bitwise equal to their own runs with
+    # the default launches.
+    import torch
+    from paper_1107_4543_amd.pool import Pool
+    s = SETS[1]
+    pool = Pool(max_members=4, max_tiles=1 << 20)
+    lats, twins = [], []
+    for i, (nx, ny) in enumerate([(1 << 20, 3), (3, 1 << 20)]):
+        lat, f = make(nx, ny, s, "f32", seed=80 + i, u0=(0.02, -0.01))
+        pool.add(lat, 13)
+        lats.append(lat)
+        twins.append(twin(lat, f, s).step(13))
+    pool.step(13)
+    done = []
+    while pool.members:
+        done += pool.poll(wait=True)
+    pool.close()
+    assert len(done) == 2
+    for lat, tw in zip(lats, twins):
+        assert lat.t == 13 and torch.equal(lat.populations(), tw.populations()), (lat.nx, lat.ny)
