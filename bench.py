@@ -473,7 +473,9 @@ def bench_serve(args):
             "steps": None, "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f32/f16", "data": "synthetic",
             "config": {"workload": "serve", "jobs_per_rate": args.jobs, "budget_gb": args.budget_gb,
-                       "rates": args.rates, "admission": "aged shortest-job-first (also sjf, fifo)"},
+                       "rates": args.rates, "admission": "aged shortest-job-first (also sjf, fifo)",
+                       "pools": "FP32/FP64 jobs (7 steps per launch) and 16-bit jobs (6 per launch), "
+                                "a job alone with its own launches"},
             "serving": out}
 
 
@@ -723,7 +725,10 @@ def main():
         budget = int(args.budget_gb * 1e9)
         serve_warmup(budget)
         row = serve_rate(100, args.served_rate, args.served_jobs, budget, ("aged",))
-        out["serving"] = dict({"workload": "serve", "budget_gb": args.budget_gb}, **row)
+        out["serving"] = dict({"workload": "serve", "budget_gb": args.budget_gb,
+                               "admission": "aged shortest-job-first",
+                               "pools": "FP32/FP64 jobs (7 steps per launch) and 16-bit jobs (6 per launch), "
+                                        "a job alone with its own launches"}, **row)
     if args.cpu_budget > 0:
         out["cpu_baseline"] = cpu_baseline(rates, fields1, cfg["nx"], cfg["ny"], w["u0x"], args.cpu_budget,
                                            args.cpu_budget_1t)
